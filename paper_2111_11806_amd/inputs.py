@@ -1,0 +1,362 @@
+"""Seeded synthetic inputs (initial states, signed distances, materials).
+
+This module is shared by the GPU path, the CPU oracle and the tests. It holds
+no arithmetic of the method itself: only grids, initial primitive fields,
+signed-distance functions of the rigid bodies and material constants. The
+conversion of a signed distance to the rigid volume fraction, every closure,
+flux and update is implemented separately on each side.
+
+Primitive field order (one plane per field, shape [nfields, nz, ny, nx]):
+``phi_l`` (N-1), ``rho_l`` (N), ``u`` (dim), ``p``, [``Vbar`` (9), ``eps_p``],
+``r``; the bracketed fields exist only for the elastoplastic system.
+
+Workloads (sizes and states as the method's own test problems prescribe):
+
+* ``sod_wall``        1D Sod tube with a static rigid wall at x = 0.85.
+* ``shock_cylinder``  2D Mach 2.8 shock over a static rigid cylinder.
+* ``air_water``       2D two-phase air/water (stiffened gases) with a rigid
+                      ellipse moving at 100 m/s through a water column.
+* ``copper_indenter`` 3D copper (Romenskii, perfect plasticity) in air with a
+                      flat-ended rigid cylinder pressed in at 200 m/s.
+* ``batch``           64 seeded 2D shock/rigid-ellipse instances.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    dim: int
+    n: tuple                      # (nx, ny, nz); unused dims are 1
+    dx: tuple                     # cell sizes (3)
+    origin: tuple                 # lower corner (3)
+    materials: List[dict]
+    solid: bool
+    bc: List[str]                 # xlo, xhi, ylo, yhi, zlo, zhi
+    W0: np.ndarray                # [nfields, nz, ny, nx]
+    bc_states: Dict[int, np.ndarray] = dataclasses.field(default_factory=dict)
+    sdf: Optional[np.ndarray] = None   # [nz, ny, nx], negative inside the body
+    width: float = 1.0
+    v_r: tuple = (0.0, 0.0, 0.0)
+    omega: tuple = (0.0, 0.0, 0.0)
+    center: tuple = (0.0, 0.0, 0.0)
+    recon: str = "bvd_thinc"
+    riemann: str = "hllc"
+    seed: str = "original"
+    probe: str = "stepout"
+    plastic: bool = True
+    thinc_beta: float = 1.6
+    lm_mach: float = 0.1
+    cfl: float = 0.4
+    t_end: float = 0.0
+
+    @property
+    def nmat(self):
+        return len(self.materials)
+
+    @property
+    def nfields(self):
+        return 2 * self.nmat + self.dim + 1 + (10 if self.solid else 0)
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.n))
+
+    def field_names(self):
+        N, D = self.nmat, self.dim
+        names = [f"phi{l}" for l in range(N - 1)] + [f"rho{l}" for l in range(N)]
+        names += ["u", "v", "w"][:D] + ["p"]
+        if self.solid:
+            names += [f"V{a}{b}" for a in range(3) for b in range(3)] + ["eps_p"]
+        return names + ["r"]
+
+    def cons_names(self):
+        N, D = self.nmat, self.dim
+        names = [f"arho{l}" for l in range(N)] + ["mx", "my", "mz"][:D] + ["E"]
+        names += [f"phi{l}" for l in range(N - 1)]
+        if self.solid:
+            names += [f"V{a}{b}" for a in range(3) for b in range(3)] + ["aeps"]
+        return names + ["r"]
+
+
+def ideal(gamma):
+    return {"kind": "ideal", "gamma": float(gamma)}
+
+
+def stiffened(gamma, pinf):
+    return {"kind": "stiffened", "gamma": float(gamma), "pinf": float(pinf)}
+
+
+def romenskii(rho0, K0, G0, alpha, beta, Gamma0, sigY=0.0):
+    return {"kind": "romenskii", "rho0": float(rho0), "K0": float(K0), "G0": float(G0),
+            "alpha": float(alpha), "beta": float(beta), "Gamma0": float(Gamma0), "sigY": float(sigY)}
+
+
+# Romenskii parameters of the method's Table 1 (SI units).
+TABLE1 = {
+    "aluminium": dict(rho0=2703.0, K0=76.3e9, G0=26.36e9, alpha=0.627, beta=2.288, Gamma0=1.484),
+    "copper": dict(rho0=8960.0, K0=130.1e9, G0=43.33e9, alpha=1.0, beta=3.0, Gamma0=2.0),
+    "steel": dict(rho0=8030.0, K0=156.2e9, G0=77.2e9, alpha=0.569, beta=2.437, Gamma0=1.563),
+}
+
+
+def _centres(n, dx, origin):
+    return [origin[a] + (np.arange(n[a]) + 0.5) * dx[a] for a in range(3)]
+
+
+def _mesh(prob_n, dx, origin):
+    xs = _centres(prob_n, dx, origin)
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    return X, Y, Z
+
+
+def normal_shock_state(M, gamma, rho1, p1):
+    """Post-shock (rho, u, p) of a shock of Mach M running into gas at rest."""
+    g = gamma
+    c1 = math.sqrt(g * p1 / rho1)
+    p2 = p1 * (1.0 + 2.0 * g / (g + 1.0) * (M * M - 1.0))
+    rho2 = rho1 * (g + 1.0) * M * M / ((g - 1.0) * M * M + 2.0)
+    S = M * c1
+    u2 = S * (1.0 - rho1 / rho2)
+    return rho2, u2, p2
+
+
+def ellipse_sdf(X, Y, cx, cy, a, b, angle=0.0):
+    """Approximate signed distance to an ellipse: (q - 1)/|grad q| with
+    q = sqrt((x'/a)^2 + (y'/b)^2) in the body frame; exact on the contour."""
+    ca, sa = math.cos(angle), math.sin(angle)
+    xr = (X - cx) * ca + (Y - cy) * sa
+    yr = -(X - cx) * sa + (Y - cy) * ca
+    q = np.sqrt((xr / a) ** 2 + (yr / b) ** 2)
+    qs = np.maximum(q, 1e-12)
+    gx = xr / (a * a * qs)
+    gy = yr / (b * b * qs)
+    gn = np.sqrt(gx * gx + gy * gy)
+    d = np.where(q > 1e-9, (q - 1.0) / np.maximum(gn, 1e-300), -min(a, b))
+    return d
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+
+def sod_wall(n=400, recon="muscl"):
+    """1D Sod tube on [0,1] with a static rigid wall r = 1 for x > 0.85."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    W = np.zeros((4, 1, 1, n))
+    left = x < 0.5
+    W[0, 0, 0] = np.where(left, 1.0, 0.125)
+    W[1, 0, 0] = 0.0
+    W[2, 0, 0] = np.where(left, 1.0, 0.1)
+    sdf = (0.85 - x).reshape(1, 1, n)
+    return Problem(name="sod_wall", dim=1, n=(n, 1, 1), dx=(dx, 1.0, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False, bc=["transmissive"] * 6, W0=W, sdf=sdf,
+                   width=1.0, recon=recon, riemann="hllc", cfl=0.8, t_end=0.3)
+
+
+def shock_cylinder(nx=1024, ny=512, mach=2.8, riemann="hllc_lm", recon="bvd_thinc", x_shock=0.15):
+    """2D Mach 2.8 planar shock (gamma 1.4, pre-shock rho = 1, p = 1) over a
+    static rigid cylinder of radius 0.1 at (0.3, 0.25) on [0,1] x [0,0.5]."""
+    dx = 1.0 / nx
+    dy = 0.5 / ny
+    X, Y, _ = _mesh((nx, ny, 1), (dx, dy, 1.0), (0.0, 0.0, 0.0))
+    rho2, u2, p2 = normal_shock_state(mach, 1.4, 1.0, 1.0)
+    post = X < x_shock
+    W = np.zeros((5, 1, ny, nx))
+    W[0] = np.where(post, rho2, 1.0)
+    W[1] = np.where(post, u2, 0.0)
+    W[2] = 0.0
+    W[3] = np.where(post, p2, 1.0)
+    sdf = np.sqrt((X - 0.3) ** 2 + (Y - 0.25) ** 2) - 0.1
+    inflow = np.array([rho2, u2, 0.0, p2, 0.0])
+    return Problem(name="shock_cylinder", dim=2, n=(nx, ny, 1), dx=(dx, dy, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False,
+                   bc=["dirichlet", "transmissive", "reflective", "reflective", "transmissive", "transmissive"],
+                   bc_states={0: inflow}, W0=W, sdf=sdf, width=1.0, recon=recon, riemann=riemann,
+                   cfl=0.4, t_end=0.3)
+
+
+def air_water(nx=2048, ny=1024, eps=1e-6):
+    """2D air/water (both stiffened gases) with a rigid ellipse (semi-axes
+    0.08 x 0.04 m at (0.25, 0.25) m) moving at 100 m/s towards a water column
+    x in [0.45, 0.65] m; p = 1e5 Pa, at rest; SI units on [0,1] x [0,0.5] m."""
+    dx = 1.0 / nx
+    dy = 0.5 / ny
+    X, Y, _ = _mesh((nx, ny, 1), (dx, dy, 1.0), (0.0, 0.0, 0.0))
+    dcol = np.maximum(0.45 - X, X - 0.65)   # negative inside the column
+    phi_w = eps + (1.0 - 2.0 * eps) * 0.5 * (1.0 - np.tanh(dcol / dx))
+    phi_air = 1.0 - phi_w
+    W = np.zeros((7, 1, ny, nx))
+    W[0] = phi_air
+    W[1] = 1.2
+    W[2] = 1000.0
+    W[3] = 0.0
+    W[4] = 0.0
+    W[5] = 1.0e5
+    sdf = ellipse_sdf(X, Y, 0.25, 0.25, 0.08, 0.04)
+    return Problem(name="air_water", dim=2, n=(nx, ny, 1), dx=(dx, dy, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[stiffened(1.4, 0.0), stiffened(4.4, 6.0e8)], solid=False,
+                   bc=["transmissive"] * 6, W0=W, sdf=sdf, width=1.0, v_r=(100.0, 0.0, 0.0),
+                   center=(0.25, 0.25, 0.0), recon="bvd_thinc", riemann="hllc", cfl=0.4, t_end=4.8e-3)
+
+
+def copper_indenter(n=256, eps=1e-6, L=25.6e-3):
+    """3D copper block (z < L/2, Romenskii, rho0 8930, G0 46 GPa, perfect
+    plasticity 0.12 GPa) under air, with a flat-ended rigid cylinder (axis z at
+    the centre, radius 20/256 of the side, flat end 0.1 mm above the copper)
+    moving at -200 m/s along z."""
+    h = L / n
+    X, Y, Z = _mesh((n, n, n), (h, h, h), (0.0, 0.0, 0.0))
+    cu = dict(TABLE1["copper"])
+    cu.update(rho0=8930.0, G0=46.0e9)
+    zc = 0.5 * L
+    phi_cu = eps + (1.0 - 2.0 * eps) * 0.5 * (1.0 - np.tanh((Z - zc) / h))
+    nf = 2 * 2 + 3 + 1 + 10
+    W = np.zeros((nf, n, n, n))
+    W[0] = phi_cu            # phi_Cu
+    W[1] = cu["rho0"]        # rho_Cu
+    W[2] = 1.2               # rho_air
+    W[3:6] = 0.0             # u
+    W[6] = 1.0e5             # p
+    for a in range(3):
+        W[7 + 4 * a] = 1.0   # Vbar = I
+    W[16] = 0.0              # eps_p
+    R = L * 20.0 / 256.0
+    z_end = zc + L / 256.0
+    rad = np.sqrt((X - 0.5 * L) ** 2 + (Y - 0.5 * L) ** 2)
+    sdf = np.maximum(rad - R, z_end - Z)
+    mats = [romenskii(cu["rho0"], cu["K0"], cu["G0"], cu["alpha"], cu["beta"], cu["Gamma0"], 0.12e9),
+            ideal(1.4)]
+    return Problem(name="copper_indenter", dim=3, n=(n, n, n), dx=(h, h, h), origin=(0.0, 0.0, 0.0),
+                   materials=mats, solid=True,
+                   bc=["transmissive", "transmissive", "transmissive", "transmissive", "reflective",
+                       "transmissive"],
+                   W0=W, sdf=sdf, width=1.0, v_r=(0.0, 0.0, -200.0), center=(0.5 * L, 0.5 * L, z_end),
+                   recon="bvd_thinc", riemann="hllc", cfl=0.3, t_end=2.5e-6)
+
+
+def batch(count=64, seed=2111, nmin=128, nmax=512, steps=200):
+    """Seeded batch of 2D ideal-gas shock / rigid-ellipse instances.
+
+    numpy default_rng(seed); per instance, in order: nx, ny ~ U{nmin..nmax};
+    Mach ~ U[1.5, 3.0]; n_bodies ~ U{1..4}; per body: centre x ~ U[0.3, 0.85],
+    y ~ U[0.15, 0.85] H, semi-axis a ~ U[0.03, 0.10], b ~ U[0.3 a, a], angle
+    ~ U[0, pi). Domain [0,1] x [0, H = ny/nx], dx = 1/nx, quiescent (1,0,0,1),
+    shock at x = 0.1, boundaries as the cylinder workload."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        nx = int(rng.integers(nmin, nmax + 1))
+        ny = int(rng.integers(nmin, nmax + 1))
+        mach = float(rng.uniform(1.5, 3.0))
+        nb = int(rng.integers(1, 5))
+        H = ny / nx
+        bodies = []
+        for _ in range(nb):
+            cx = float(rng.uniform(0.3, 0.85))
+            cy = float(rng.uniform(0.15, 0.85)) * H
+            a = float(rng.uniform(0.03, 0.10))
+            b = float(rng.uniform(0.3 * a, a))
+            ang = float(rng.uniform(0.0, math.pi))
+            bodies.append((cx, cy, a, b, ang))
+        dx = 1.0 / nx
+        X, Y, _ = _mesh((nx, ny, 1), (dx, dx, 1.0), (0.0, 0.0, 0.0))
+        rho2, u2, p2 = normal_shock_state(mach, 1.4, 1.0, 1.0)
+        post = X < 0.1
+        W = np.zeros((5, 1, ny, nx))
+        W[0] = np.where(post, rho2, 1.0)
+        W[1] = np.where(post, u2, 0.0)
+        W[3] = np.where(post, p2, 1.0)
+        sdf = np.min(np.stack([ellipse_sdf(X, Y, *bd) for bd in bodies]), axis=0)
+        p = Problem(name=f"batch{k}", dim=2, n=(nx, ny, 1), dx=(dx, dx, 1.0), origin=(0.0, 0.0, 0.0),
+                    materials=[ideal(1.4)], solid=False,
+                    bc=["dirichlet", "transmissive", "reflective", "reflective", "transmissive", "transmissive"],
+                    bc_states={0: np.array([rho2, u2, 0.0, p2, 0.0])}, W0=W, sdf=sdf, width=1.0,
+                    recon="bvd_thinc", riemann="hllc_lm", cfl=0.4, t_end=1e9)
+        out.append(p)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Verification problems
+# ---------------------------------------------------------------------------
+
+def riemann_1d(left, right, materials, n=400, x0=0.5, length=1.0, t_end=0.2, cfl=0.5,
+               recon="muscl", riemann="hllc", nfields=None):
+    """1D shock tube with primitive left/right states (full W vectors without r)."""
+    dx = length / n
+    x = (np.arange(n) + 0.5) * dx
+    left = np.asarray(left, float)
+    right = np.asarray(right, float)
+    nf = len(left) + 1
+    W = np.zeros((nf, 1, 1, n))
+    for q in range(nf - 1):
+        W[q, 0, 0] = np.where(x < x0, left[q], right[q])
+    return Problem(name="riemann", dim=1, n=(n, 1, 1), dx=(dx, 1.0, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=materials, solid=False, bc=["transmissive"] * 6, W0=W, recon=recon,
+                   riemann=riemann, cfl=cfl, t_end=t_end, seed="none")
+
+
+def piston_1d(n=400, v_p=1.0, x_p=0.2, t_end=0.3, recon="muscl"):
+    """Rigid piston (body x < x_p) moving at v_p into gas at rest (1, 0, 1)."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    W = np.zeros((4, 1, 1, n))
+    W[0] = 1.0
+    W[2] = 1.0
+    sdf = (x - x_p).reshape(1, 1, n)
+    return Problem(name="piston", dim=1, n=(n, 1, 1), dx=(dx, 1.0, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False, bc=["transmissive"] * 6, W0=W, sdf=sdf, width=1.0,
+                   v_r=(v_p, 0.0, 0.0), center=(x_p, 0.0, 0.0), recon=recon, riemann="hllc", cfl=0.5,
+                   t_end=t_end)
+
+
+def quiescent_body(nx=64, ny=48, recon="bvd_thinc", riemann="hllc", seed="original"):
+    """Gas at rest around a static rigid ellipse, reflective walls."""
+    dx = 1.0 / nx
+    X, Y, _ = _mesh((nx, ny, 1), (dx, dx, 1.0), (0.0, 0.0, 0.0))
+    W = np.zeros((5, 1, ny, nx))
+    W[0] = 1.4
+    W[3] = 1.0
+    sdf = ellipse_sdf(X, Y, 0.45, 0.5 * ny * dx, 0.2, 0.12, 0.3)
+    return Problem(name="quiescent", dim=2, n=(nx, ny, 1), dx=(dx, dx, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False, bc=["reflective"] * 6, W0=W, sdf=sdf, width=1.0,
+                   recon=recon, riemann=riemann, seed=seed, cfl=0.4, t_end=1.0)
+
+
+def periodic_box(dim=2, n=32, nmat=1, seed=7, recon="bvd_thinc", riemann="hllc"):
+    """Smooth random periodic state without rigid bodies (r = 0)."""
+    rng = np.random.default_rng(seed)
+    shape = (n if dim > 2 else 1, n if dim > 1 else 1, n)
+    dx = 1.0 / n
+    X, Y, Z = _mesh((n, shape[1], shape[0]), (dx, dx, dx), (0.0, 0.0, 0.0))
+    def smooth():
+        a = rng.uniform(-1, 1, 3)
+        return a[0] * np.sin(2 * np.pi * X + a[1]) + a[2] * np.cos(2 * np.pi * (Y + Z) + a[0])
+    if nmat == 1:
+        mats = [ideal(1.4)]
+    else:
+        mats = [stiffened(1.4, 0.0), stiffened(4.4, 6.0)]
+    nf = 2 * nmat + dim + 1
+    W = np.zeros((nf,) + shape)
+    q = 0
+    if nmat == 2:
+        W[q] = 0.5 + 0.3 * np.tanh(3 * smooth()); q += 1
+        W[q] = 1.0 + 0.2 * smooth(); q += 1
+        W[q] = 3.0 + 0.5 * smooth(); q += 1
+    else:
+        W[q] = 1.0 + 0.3 * np.tanh(smooth()); q += 1
+    for a in range(dim):
+        W[q] = 0.3 * smooth(); q += 1
+    W[q] = 1.0 + 0.2 * np.tanh(smooth()); q += 1
+    W[q] = 0.0
+    return Problem(name="periodic", dim=dim, n=(n, shape[1], shape[0]), dx=(dx, dx, dx), origin=(0.0, 0.0, 0.0),
+                   materials=mats, solid=False, bc=["periodic"] * 6, W0=W, recon=recon, riemann=riemann,
+                   seed="none", cfl=0.4, t_end=1.0)
