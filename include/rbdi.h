@@ -1,0 +1,221 @@
+/*
+ * rbdi.h -- C ABI of librbdi, the MI355X (gfx950) implementation of the
+ * Eulerian finite-volume step of the diffuse-interface rigid-body method of
+ * Wallis, Barton & Nikiforakis (arXiv 2111.11806).
+ *
+ * One time step (rbdi_step) is, in this order:
+ *   1. interface seeding of rigid cells (Sec. 3.2, the seeding routine; once
+ *      per step, before the hyperbolic update);
+ *   2. three SSP-RK3 stages (Sec. 3.1, third-order Runge-Kutta), each one
+ *      evaluation of the unsplit semi-discrete operator D (Sec. 3.1, spatial
+ *      operator) built from direction sweeps: per-cell closure (Sec. 2.2),
+ *      MUSCL-BVD-THINC reconstruction of the primitive variables, r
+ *      included (Sec. 3.1), HLLC / HLLC-LM fluxes (Sec. 3.1, Sec. 4.3), the
+ *      upwind r flux and the non-conservative terms (Sec. 3.1), and the
+ *      conservative update; thermodynamic fields of rigid (r > 0.5) cells
+ *      are not updated (Sec. 3.1).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: RBDI_OK (0) or a negative rbdi_error. The message of the
+ *    last failure on the calling thread is rbdi_last_error().
+ *  - Arrays of cell data are structure-of-arrays over the INTERIOR cells:
+ *    [nfields][nz][ny][nx], x fastest, FP64 at the API in every precision.
+ *  - Primitive field order: phi_l (N-1), rho_l (N), u (dim), p,
+ *    [Vbar (9, row major), eps_p], r. Conserved field order: phi_l rho_l (N),
+ *    rho u (dim), rho E, phi_l (N-1), [Vbar (9), phi_s rho_s eps_p], r.
+ *    Bracketed fields exist only when desc.solid = 1.
+ *  - Pointers marked "host or device" are read on the device when the
+ *    on_device argument is nonzero (device pointers of the handle's GPU),
+ *    otherwise they are host pointers. The library never keeps or frees
+ *    caller memory.
+ *  - Every GPU operation is enqueued on the handle's stream (rbdi_set_stream;
+ *    default: the null stream). Entry points that return device results to
+ *    the host (compute_dt, status, rigid_force, conserved_totals, get_state*)
+ *    synchronise that stream; rbdi_step and rbdi_advance do not.
+ *  - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef RBDI_H
+#define RBDI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBDI_API __attribute__((visibility("default")))
+
+typedef struct rbdi_handle rbdi_handle;
+
+typedef enum {
+  RBDI_OK = 0,
+  RBDI_ERR_BAD_ARG = -1,     /* invalid argument; nothing was enqueued */
+  RBDI_ERR_OOM = -2,         /* device allocation failed */
+  RBDI_ERR_HIP = -3,         /* a HIP runtime call failed */
+  RBDI_ERR_NONPHYSICAL = -4, /* a cell left the admissible set (rbdi_status) */
+  RBDI_ERR_NOT_READY = -5,   /* call order violated (e.g. step before state) */
+  RBDI_ERR_UNSUPPORTED = -6  /* this build has no kernel for the combination */
+} rbdi_error;
+
+enum { RBDI_EOS_IDEAL = 0, RBDI_EOS_STIFFENED = 1, RBDI_EOS_ROMENSKII = 2 };
+enum { RBDI_BC_TRANSMISSIVE = 0, RBDI_BC_REFLECTIVE = 1, RBDI_BC_DIRICHLET = 2, RBDI_BC_PERIODIC = 3 };
+enum { RBDI_RECON_MUSCL = 0, RBDI_RECON_BVD_THINC = 1 };
+enum { RBDI_RIEMANN_HLLC = 0, RBDI_RIEMANN_HLLC_LM = 1 };
+enum { RBDI_SEED_ORIGINAL = 0, RBDI_SEED_RIEMANN = 1, RBDI_SEED_NONE = 2 };
+enum { RBDI_PROBE_STEPOUT = 0, RBDI_PROBE_FIXED = 1 };
+enum { RBDI_FP64 = 0, RBDI_FP32 = 1 };
+
+/* Grid, system and scheme of one instance.
+ * dim 1..3; n[d] interior cells (n[d] = 1 for d >= dim); dx[d] cell size;
+ * origin: coordinates of the lower domain corner.
+ * nmat 1..2 materials; solid = 1 adds the stretch tensor Vbar and the plastic
+ * strain of the first Romenskii material (elastoplastic system, Sec. 2.1.1).
+ * bc[6]: x-lo, x-hi, y-lo, y-hi, z-lo, z-hi, one of RBDI_BC_*.
+ * recon: RBDI_RECON_*; riemann: RBDI_RIEMANN_*; seed: RBDI_SEED_*;
+ * probe: RBDI_PROBE_*; plastic: apply the plastic return (solid only);
+ * thinc_beta: THINC steepness; lm_mach: HLLC-LM Mach limit;
+ * precision: RBDI_FP64, or RBDI_FP32 (flux and reconstruction in FP32; the
+ * mixture-pressure inversion, dt, force/torque and totals in FP64). */
+typedef struct {
+  int dim;
+  int n[3];
+  double dx[3];
+  double origin[3];
+  int nmat;
+  int solid;
+  int bc[6];
+  int recon;
+  int riemann;
+  int seed;
+  int probe;
+  int plastic;
+  double thinc_beta;
+  double lm_mach;
+  int precision;
+} rbdi_desc;
+
+/* Equation of state of one material (Sec. 2.1.3 and the Mie-Gruneisen form of
+ * Sec. 2.1.2). IDEAL: gamma. STIFFENED: gamma, pinf (e_ref = pinf/rho,
+ * p_ref = -pinf). ROMENSKII: rho0, K0, G0, alpha, beta, Gamma0 (Table 1) and
+ * the perfect-plasticity yield stress sigma_y (0 = elastic). SI or
+ * non-dimensional units, consistently. */
+typedef struct {
+  int kind;
+  double gamma, pinf;
+  double rho0, K0, G0, alpha, beta, Gamma0, sigma_y;
+} rbdi_eos;
+
+/* Counters of the device-side path, read by rbdi_status. */
+typedef struct {
+  long long steps;        /* completed steps */
+  double t;               /* simulated time */
+  double last_dt;         /* dt of the last step */
+  long long band_cells;   /* rigid cells with a nonzero normal (last seeding) */
+  long long seeded;       /* cells seeded (cumulative) */
+  long long probe_fail;   /* rigid band cells without a valid probe (cumulative) */
+  int nonphysical;        /* 1 once a non-admissible updated cell was found */
+  long long first_bad;    /* linear interior index of the first such cell, or -1 */
+} rbdi_stats;
+
+/* Create an instance on the current HIP device. Allocates every device buffer
+ * the handle owns (three state copies plus scratch); *out receives the
+ * handle, which rbdi_destroy releases. Errors: BAD_ARG (invalid desc),
+ * OOM, HIP. */
+RBDI_API int rbdi_create(const rbdi_desc* desc, rbdi_handle** out);
+
+/* Release the handle and its device memory (synchronises its stream). */
+RBDI_API int rbdi_destroy(rbdi_handle* h);
+
+/* Number of primitive (= conserved) fields of the instance. */
+RBDI_API int rbdi_nfields(const rbdi_handle* h);
+
+/* Enqueue all further work on the given hipStream_t (passed as void*; NULL =
+ * the null stream). The caller keeps the stream alive while it is set. */
+RBDI_API int rbdi_set_stream(rbdi_handle* h, void* hip_stream);
+
+/* Material l (0 <= l < nmat). Must precede rbdi_set_state_prim. BAD_ARG for
+ * gamma <= 1, rho0 <= 0, K0 < 0, a solid kind without desc.solid, etc. */
+RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* eos);
+
+/* Primitive state imposed on the ghost cells of a Dirichlet face (face 0..5),
+ * host array of nfields values. */
+RBDI_API int rbdi_set_bc_state(rbdi_handle* h, int face, const double* W);
+
+/* Set the interior state from primitives W (host or device, FP64, SoA over
+ * interior cells). Converted to conserved variables on the device. */
+RBDI_API int rbdi_set_state_prim(rbdi_handle* h, const double* W, int on_device);
+
+/* Read the interior state as primitives / conserved variables into W / U
+ * (host or device, FP64). Synchronises the stream. */
+RBDI_API int rbdi_get_state_prim(rbdi_handle* h, double* W, int on_device);
+RBDI_API int rbdi_get_state_cons(rbdi_handle* h, double* U, int on_device);
+
+/* Set the conserved interior state directly (host or device, FP64). */
+RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device);
+
+/* Rigid volume fraction from a signed distance sdf (host or device, FP64,
+ * one value per interior cell, negative inside the body; union of bodies =
+ * pointwise minimum): r = (1 - tanh(sdf / (width dx_min))) / 2 (Sec. 2.3
+ * represents bodies by a scalar field r in [0,1] whose 0.5 contour is the
+ * surface). The imposed rigid velocity is v_r(x) = v + omega x (x - center)
+ * (Sec. 2.3); center moves with v after every step. */
+RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device, double width,
+                                const double v[3], const double omega[3], const double center[3]);
+
+/* Replace the rigid motion (velocity, angular velocity, centre). */
+RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3],
+                                   const double center[3]);
+
+/* CFL time step: dt = cfl * min over non-rigid cells and directions of
+ * dx_d / max(|u_d| + c, |v_r,d|) (Sec. 3: a fraction of the global maximum
+ * stable step; mixture sound speed of Sec. 2.2). FP64 deterministic
+ * reduction; synchronises the stream. NONPHYSICAL if no finite value. */
+RBDI_API int rbdi_compute_dt(rbdi_handle* h, double cfl, double* dt);
+
+/* Enqueue one time step of size dt (seeding + three RK stages). Returns after
+ * enqueueing; device-side failures are reported by rbdi_status. */
+RBDI_API int rbdi_step(rbdi_handle* h, double dt);
+
+/* Enqueue nsteps steps whose dt is computed on the device from the CFL
+ * condition (as rbdi_compute_dt) and clipped so that t does not pass t_end;
+ * no host synchronisation between steps. Steps after t reaches t_end do no
+ * work. */
+RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end);
+
+/* Synchronise and read the counters; returns NONPHYSICAL if a non-admissible
+ * cell was flagged (st is filled either way). */
+RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st);
+
+/* Force and torque about center exerted by the material on the rigid body,
+ * FP64, deterministic: F = sum_i (-sigma_i . grad_h r_i) dV and
+ * T = sum_i (x_i - center) x (-sigma_i . grad_h r_i) dV over interior cells
+ * (central differences; the paper's bodies are one-way and it defines no
+ * load, so this diffuse-surface integral is this library's definition).
+ * Synchronises the stream. */
+RBDI_API int rbdi_rigid_force(rbdi_handle* h, const double center[3], double F[3], double T[3]);
+
+/* FP64 totals of every conserved field times the cell volume: out[0..n) over
+ * all interior cells, out[n..2n) over non-rigid (r <= 0.5) cells.
+ * Synchronises the stream. */
+RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
+
+/* Kernel timing (profiling aid). When enabled, every launch of the classes
+ * below is bracketed by a HIP event pair on the handle's stream; the events
+ * are kept until rbdi_kernel_times, which synchronises the stream, adds the
+ * elapsed times per class into ms[class] (milliseconds) and launches[class],
+ * and releases the recorded pairs. Classes: 0 sweep along x (the last sweep,
+ * with the RK combine), 1 sweep along y, 2 sweep along z, 3 seeding, 4 rigid
+ * band compaction, 5 CFL reduction. ms and launches hold RBDI_NUM_KCLASS
+ * entries each. */
+#define RBDI_NUM_KCLASS 6
+RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable);
+RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+RBDI_API const char* rbdi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBDI_H */

@@ -1,0 +1,600 @@
+// rbdi_api.hip -- host side of librbdi: the C ABI declared in include/rbdi.h.
+// Validates arguments, owns device buffers, and enqueues the kernels of
+// rbdi_kernels.hpp on the handle's stream. Instantiated for the systems
+// (dimension, materials, elastoplastic) and precisions the library supports.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rbdi.h"
+#include "rbdi_kernels.hpp"
+
+using namespace rbdi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(RBDI_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Ops;
+
+}  // namespace
+
+struct rbdi_handle {
+  rbdi_desc desc;
+  Params P;
+  int nf = 0;
+  int elem = 8;            // bytes per stored value
+  void* U[3] = {nullptr, nullptr, nullptr};
+  void* D = nullptr;
+  double* stage_buf = nullptr;  // FP64 staging for API transfers (nf * ncell)
+  int* band = nullptr;
+  DevScalars* sc = nullptr;
+  double* part = nullptr;       // reduction partials
+  double* red_out = nullptr;    // reduction results (device)
+  hipStream_t stream = nullptr;
+  bool have_mat[kMaxMat] = {false, false};
+  bool have_state = false;
+  bool band_valid = false;
+  bool dynamic_r = false;
+  double t_host = 0.0;
+  const Ops* ops = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  std::vector<int> ev_cls;      // class of each recorded pair
+  size_t ev_used = 0;
+};
+
+namespace {
+
+// Brackets one launch with an event pair when kernel timing is enabled.
+struct Timed {
+  rbdi_handle* h;
+  size_t slot = (size_t)-1;
+  Timed(rbdi_handle* hh, int cls) : h(hh) {
+    if (!h->timing) return;
+    if (h->ev_used * 2 + 2 > h->ev.size()) {
+      for (int k = 0; k < 256; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        h->ev.push_back(e);
+      }
+    }
+    slot = h->ev_used++;
+    if (h->ev_cls.size() < h->ev_used) h->ev_cls.resize(h->ev_used);
+    h->ev_cls[slot] = cls;
+    (void)hipEventRecord(h->ev[2 * slot], h->stream);
+  }
+  ~Timed() {
+    if (slot != (size_t)-1) (void)hipEventRecord(h->ev[2 * slot + 1], h->stream);
+  }
+};
+
+}  // namespace
+
+namespace {
+
+struct Ops {
+  void (*prim_to_state)(rbdi_handle*, const double*);
+  void (*state_to_prim)(rbdi_handle*, double*);
+  void (*state_to_f64)(rbdi_handle*, double*);
+  void (*f64_to_state)(rbdi_handle*, const double*);
+  void (*r_from_sdf)(rbdi_handle*, const double*, double);
+  void (*band)(rbdi_handle*);
+  void (*seed)(rbdi_handle*);
+  void (*stages)(rbdi_handle*);
+  void (*dt_partial)(rbdi_handle*);
+  void (*force)(rbdi_handle*, const double*);
+  void (*totals)(rbdi_handle*);
+};
+
+inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <class S, typename T>
+struct Impl {
+  static T* u(rbdi_handle* h, int k) { return static_cast<T*>(h->U[k]); }
+
+  static void prim_to_state(rbdi_handle* h, const double* W) {
+    hipLaunchKernelGGL((k_prim_to_state<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       W, u(h, 0));
+  }
+  static void state_to_prim(rbdi_handle* h, double* W) {
+    hipLaunchKernelGGL((k_state_to_prim<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       (const T*)u(h, 0), W);
+  }
+  static void state_to_f64(rbdi_handle* h, double* out) {
+    hipLaunchKernelGGL((k_state_to_f64<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       (const T*)u(h, 0), out);
+  }
+  static void f64_to_state(rbdi_handle* h, const double* in) {
+    hipLaunchKernelGGL((k_f64_to_state<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       in, u(h, 0));
+  }
+  static void r_from_sdf(rbdi_handle* h, const double* sdf, double inv_w) {
+    hipLaunchKernelGGL((k_r_from_sdf<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       sdf, inv_w, u(h, 0));
+  }
+  static void band(rbdi_handle* h) {
+    Timed tm(h, 4);
+    hipLaunchKernelGGL(k_reset_band, dim3(1), dim3(1), 0, h->stream, h->sc);
+    hipLaunchKernelGGL((k_band<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
+                       (const T*)u(h, 0), h->band, h->sc);
+    hipLaunchKernelGGL(k_band_stat, dim3(1), dim3(1), 0, h->stream, h->sc);
+  }
+  static void seed(rbdi_handle* h) {
+    Timed tm(h, 3);
+    hipLaunchKernelGGL((k_seed<S, T>), dim3(512), dim3(256), 0, h->stream, h->P, u(h, 0), (const int*)h->band,
+                       h->sc);
+  }
+  template <int DIR, int MODE>
+  static void sweep(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, double b, int stage) {
+    const Params& P = h->P;
+    const int nd = P.n[DIR];
+    const unsigned nseg = (unsigned)((nd + kOut - 1) / kOut);
+    const int wpb = S::D == 1 ? 1 : kWPB;
+    dim3 grid;
+    if (DIR == 0) grid = dim3(nseg, (unsigned)((P.n[1] + wpb - 1) / wpb), (unsigned)P.n[2]);
+    else if (DIR == 1) grid = dim3((unsigned)((P.n[0] + wpb - 1) / wpb), nseg, (unsigned)P.n[2]);
+    else grid = dim3((unsigned)((P.n[0] + wpb - 1) / wpb), (unsigned)P.n[1], nseg);
+    Timed tm(h, DIR);
+    hipLaunchKernelGGL((k_sweep<S, T, DIR, MODE>), grid, dim3(kWave * wpb), 0, h->stream, P, Uin, U0,
+                       static_cast<T*>(h->D), Uout, h->sc, b, stage);
+  }
+  static void stages(rbdi_handle* h) {
+    const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
+    const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
+    for (int s = 0; s < 3; ++s) {
+      const T* Uin = u(h, in_[s]);
+      const T* U0 = u(h, 0);
+      T* Uout = u(h, out_[s]);
+      if constexpr (S::D == 3) {
+        sweep<2, 0>(h, Uin, U0, Uout, bc[s], s);
+        sweep<1, 1>(h, Uin, U0, Uout, bc[s], s);
+        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
+      } else if constexpr (S::D == 2) {
+        sweep<1, 0>(h, Uin, U0, Uout, bc[s], s);
+        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
+      } else {
+        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
+      }
+    }
+  }
+  static void dt_partial(rbdi_handle* h) {
+    Timed tm(h, 5);
+    hipLaunchKernelGGL((k_dt_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
+                       (const T*)u(h, 0), (const DevScalars*)h->sc, h->part);
+  }
+  static void force(rbdi_handle* h, const double* c) {
+    hipLaunchKernelGGL((k_force_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
+                       (const T*)u(h, 0), c[0], c[1], c[2], h->part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, h->stream, (const double*)h->part, kRedBlocks, 6,
+                       h->red_out);
+  }
+  static void totals(rbdi_handle* h) {
+    hipLaunchKernelGGL((k_totals_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
+                       (const T*)u(h, 0), h->part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, h->stream, (const double*)h->part, kRedBlocks,
+                       2 * S::NF, h->red_out);
+  }
+  static const Ops* ops() {
+    static const Ops o = {prim_to_state, state_to_prim, state_to_f64, f64_to_state, r_from_sdf, band, seed,
+                          stages, dt_partial, force, totals};
+    return &o;
+  }
+};
+
+template <typename T>
+const Ops* pick(int dim, int nmat, int solid) {
+  if (!solid) {
+    if (dim == 1 && nmat == 1) return Impl<Sys<1, 1, false>, T>::ops();
+    if (dim == 1 && nmat == 2) return Impl<Sys<1, 2, false>, T>::ops();
+    if (dim == 2 && nmat == 1) return Impl<Sys<2, 1, false>, T>::ops();
+    if (dim == 2 && nmat == 2) return Impl<Sys<2, 2, false>, T>::ops();
+    if (dim == 3 && nmat == 1) return Impl<Sys<3, 1, false>, T>::ops();
+    if (dim == 3 && nmat == 2) return Impl<Sys<3, 2, false>, T>::ops();
+  } else {
+    if (dim == 1 && nmat == 2) return Impl<Sys<1, 2, true>, T>::ops();
+    if (dim == 2 && nmat == 2) return Impl<Sys<2, 2, true>, T>::ops();
+    if (dim == 3 && nmat == 2) return Impl<Sys<3, 2, true>, T>::ops();
+  }
+  return nullptr;
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RBDI_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return RBDI_OK;
+}
+
+void free_all(rbdi_handle* h) {
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+  for (auto& p : h->U)
+    if (p) { (void)hipFree(p); p = nullptr; }
+  void* ptrs[] = {h->D, h->stage_buf, h->band, h->sc, h->part, h->red_out};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->D = nullptr; h->stage_buf = nullptr; h->band = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+RBDI_API const char* rbdi_last_error(void) { return g_err.c_str(); }
+
+RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
+  if (!d || !out) return fail(RBDI_ERR_BAD_ARG, "null desc or out");
+  *out = nullptr;
+  if (d->dim < 1 || d->dim > 3) return fail(RBDI_ERR_BAD_ARG, "dim must be 1..3");
+  if (d->nmat < 1 || d->nmat > kMaxMat) return fail(RBDI_ERR_BAD_ARG, "nmat must be 1..2");
+  if (d->precision != RBDI_FP64 && d->precision != RBDI_FP32) return fail(RBDI_ERR_BAD_ARG, "bad precision");
+  long long ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int na = a < d->dim ? d->n[a] : 1;
+    if (na < 1 || (a >= d->dim && d->n[a] != 1)) return fail(RBDI_ERR_BAD_ARG, "bad grid size");
+    if (a < d->dim && !(d->dx[a] > 0.0)) return fail(RBDI_ERR_BAD_ARG, "dx must be positive");
+    ncell *= na;
+  }
+  if (ncell >= (1LL << 31)) return fail(RBDI_ERR_BAD_ARG, "too many cells for 32-bit band indices");
+  for (int q = 0; q < 6; ++q) {
+    if (d->bc[q] < 0 || d->bc[q] > 3) return fail(RBDI_ERR_BAD_ARG, "bad boundary condition");
+    if (q / 2 < d->dim && d->bc[q] == RBDI_BC_REFLECTIVE && d->n[q / 2] < kHalo)
+      return fail(RBDI_ERR_BAD_ARG, "reflective boundary needs at least 3 cells");
+    if (q / 2 < d->dim && (d->bc[q] == RBDI_BC_PERIODIC) != (d->bc[q ^ 1] == RBDI_BC_PERIODIC))
+      return fail(RBDI_ERR_BAD_ARG, "periodic boundaries must be paired");
+  }
+  if (d->recon < 0 || d->recon > 1 || d->riemann < 0 || d->riemann > 1 || d->seed < 0 || d->seed > 2 ||
+      d->probe < 0 || d->probe > 1)
+    return fail(RBDI_ERR_BAD_ARG, "bad scheme option");
+  if (d->recon == RBDI_RECON_BVD_THINC && !(d->thinc_beta > 0.0)) return fail(RBDI_ERR_BAD_ARG, "thinc_beta must be > 0");
+  if (d->riemann == RBDI_RIEMANN_HLLC_LM && !(d->lm_mach > 0.0)) return fail(RBDI_ERR_BAD_ARG, "lm_mach must be > 0");
+  const Ops* ops = d->precision == RBDI_FP64 ? pick<double>(d->dim, d->nmat, d->solid)
+                                             : pick<float>(d->dim, d->nmat, d->solid);
+  if (!ops) return fail(RBDI_ERR_UNSUPPORTED, "no kernels for this (dim, nmat, solid) combination");
+
+  rbdi_handle* h = new rbdi_handle();
+  h->desc = *d;
+  h->ops = ops;
+  h->nf = 2 * d->nmat + d->dim + 1 + (d->solid ? 10 : 0);
+  h->elem = d->precision == RBDI_FP64 ? 8 : 4;
+  Params& P = h->P;
+  std::memset(&P, 0, sizeof(P));
+  P.dim = d->dim;
+  P.dmin = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = a < d->dim ? d->n[a] : 1;
+    P.dx[a] = a < d->dim ? d->dx[a] : 1.0;
+    P.inv_dx[a] = 1.0 / P.dx[a];
+    P.x0[a] = d->origin[a];
+    if (a < d->dim) P.dmin = std::fmin(P.dmin, P.dx[a]);
+  }
+  P.st[0] = 1;
+  P.st[1] = P.n[0];
+  P.st[2] = (long long)P.n[0] * P.n[1];
+  P.ncell = ncell;
+  P.fs = (ncell + 63) / 64 * 64;
+  for (int q = 0; q < 6; ++q) P.bc[q] = q / 2 < d->dim ? d->bc[q] : RBDI_BC_TRANSMISSIVE;
+  P.recon = d->recon;
+  P.riemann = d->riemann;
+  P.seed = d->seed;
+  P.probe = d->probe;
+  P.plastic = d->plastic;
+  P.beta = d->thinc_beta;
+  P.cosh_b = std::cosh(d->thinc_beta);
+  P.inv_sinh_b = 1.0 / std::sinh(d->thinc_beta);
+  P.tanh_b = std::tanh(d->thinc_beta);
+  P.lm_mach = d->lm_mach;
+  P.solid_phase = -1;
+
+  const size_t state_bytes = (size_t)P.fs * h->nf * h->elem;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMalloc(&h->U[k], state_bytes);
+  if (e == hipSuccess) e = hipMalloc(&h->D, state_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->stage_buf, (size_t)ncell * h->nf * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&h->band, (size_t)ncell * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&h->sc, sizeof(DevScalars));
+  if (e == hipSuccess) e = hipMalloc((void**)&h->part, sizeof(double) * kRedBlocks * 2 * kMaxF);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->red_out, sizeof(double) * 2 * kMaxF);
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(e == hipErrorOutOfMemory ? RBDI_ERR_OOM : RBDI_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  DevScalars zero{};
+  zero.first_bad = -1;
+  e = hipMemcpy(h->sc, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(h->U[0], 0, state_bytes);
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(RBDI_ERR_HIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_destroy(rbdi_handle* h) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_nfields(const rbdi_handle* h) { return h ? h->nf : RBDI_ERR_BAD_ARG; }
+
+RBDI_API int rbdi_set_stream(rbdi_handle* h, void* s) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  h->stream = static_cast<hipStream_t>(s);
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* e) {
+  if (!h || !e) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (l < 0 || l >= h->desc.nmat) return fail(RBDI_ERR_BAD_ARG, "material index out of range");
+  MatDev m{};
+  m.kind = e->kind;
+  if (e->kind == RBDI_EOS_IDEAL || e->kind == RBDI_EOS_STIFFENED) {
+    if (!(e->gamma > 1.0)) return fail(RBDI_ERR_BAD_ARG, "gamma must be > 1");
+    const double pinf = e->kind == RBDI_EOS_STIFFENED ? e->pinf : 0.0;
+    if (!(pinf >= 0.0)) return fail(RBDI_ERR_BAD_ARG, "pinf must be >= 0");
+    m.gamma = e->gamma;
+    m.pinf = pinf;
+    m.Gam = e->gamma - 1.0;
+    m.invGam = 1.0 / m.Gam;
+    m.Bfl = e->gamma * pinf / m.Gam;
+  } else if (e->kind == RBDI_EOS_ROMENSKII) {
+    if (!h->desc.solid) return fail(RBDI_ERR_BAD_ARG, "Romenskii material needs desc.solid = 1");
+    if (!(e->rho0 > 0.0) || !(e->K0 >= 0.0) || !(e->G0 >= 0.0) || !(e->alpha > 0.0) || !(e->Gamma0 > 0.0) ||
+        !(e->sigma_y >= 0.0))
+      return fail(RBDI_ERR_BAD_ARG, "bad Romenskii parameters");
+    m.rho0 = e->rho0;
+    m.invrho0 = 1.0 / e->rho0;
+    m.K0 = e->K0;
+    m.G0 = e->G0;
+    m.alpha = e->alpha;
+    m.beta = e->beta;
+    m.kc = e->K0 / (2.0 * e->alpha * e->alpha);
+    m.Gam = e->Gamma0;
+    m.invGam = 1.0 / e->Gamma0;
+    m.sigY = e->sigma_y;
+    if (h->P.solid_phase < 0 || h->P.solid_phase == l) h->P.solid_phase = l;
+  } else {
+    return fail(RBDI_ERR_BAD_ARG, "unknown EOS kind");
+  }
+  h->P.mat[l] = m;
+  h->have_mat[l] = true;
+  return RBDI_OK;
+}
+
+static int ready_materials(rbdi_handle* h) {
+  for (int l = 0; l < h->desc.nmat; ++l)
+    if (!h->have_mat[l]) return fail(RBDI_ERR_NOT_READY, "set every material first");
+  if (h->desc.solid && h->P.solid_phase < 0) return fail(RBDI_ERR_NOT_READY, "solid system needs a Romenskii material");
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_set_bc_state(rbdi_handle* h, int face, const double* W) {
+  if (!h || !W) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (face < 0 || face > 5) return fail(RBDI_ERR_BAD_ARG, "face must be 0..5");
+  for (int q = 0; q < h->nf; ++q) {
+    if (!std::isfinite(W[q])) return fail(RBDI_ERR_BAD_ARG, "non-finite boundary state");
+    h->P.bcW[face][q] = W[q];
+  }
+  return RBDI_OK;
+}
+
+static int stage_in(rbdi_handle* h, const double* src, int on_device) {
+  const size_t bytes = (size_t)h->P.ncell * h->nf * sizeof(double);
+  HIP_OK(hipMemcpyAsync(h->stage_buf, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        h->stream));
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_set_state_prim(rbdi_handle* h, const double* W, int on_device) {
+  if (!h || !W) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  int rc = ready_materials(h);
+  if (rc) return rc;
+  rc = stage_in(h, W, on_device);
+  if (rc) return rc;
+  h->ops->prim_to_state(h, h->stage_buf);
+  h->have_state = true;
+  h->band_valid = false;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return check_launch();
+}
+
+RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device) {
+  if (!h || !U) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  int rc = ready_materials(h);
+  if (rc) return rc;
+  rc = stage_in(h, U, on_device);
+  if (rc) return rc;
+  h->ops->f64_to_state(h, h->stage_buf);
+  h->have_state = true;
+  h->band_valid = false;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return check_launch();
+}
+
+static int stage_out(rbdi_handle* h, double* dst, int on_device) {
+  const size_t bytes = (size_t)h->P.ncell * h->nf * sizeof(double);
+  HIP_OK(hipMemcpyAsync(dst, h->stage_buf, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return check_launch();
+}
+
+RBDI_API int rbdi_get_state_prim(rbdi_handle* h, double* W, int on_device) {
+  if (!h || !W) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->state_to_prim(h, h->stage_buf);
+  return stage_out(h, W, on_device);
+}
+
+RBDI_API int rbdi_get_state_cons(rbdi_handle* h, double* U, int on_device) {
+  if (!h || !U) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->state_to_f64(h, h->stage_buf);
+  return stage_out(h, U, on_device);
+}
+
+RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device, double width, const double v[3],
+                                const double omega[3], const double center[3]) {
+  if (!h || !sdf || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!(width > 0.0)) return fail(RBDI_ERR_BAD_ARG, "width must be > 0");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "set the state before the rigid field");
+  const size_t bytes = (size_t)h->P.ncell * sizeof(double);
+  HIP_OK(hipMemcpyAsync(h->stage_buf, sdf, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        h->stream));
+  h->ops->r_from_sdf(h, h->stage_buf, 1.0 / (width * h->P.dmin));
+  int rc = rbdi_set_rigid_motion(h, v, omega, center);
+  if (rc) return rc;
+  h->band_valid = false;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return check_launch();
+}
+
+__global__ void k_set_motion_time(DevScalars* sc) { sc->t_motion = sc->t; }
+
+RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3], const double center[3]) {
+  if (!h || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  bool moving = false;
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(v[a]) || !std::isfinite(omega[a]) || !std::isfinite(center[a]))
+      return fail(RBDI_ERR_BAD_ARG, "non-finite rigid motion");
+    h->P.vr[a] = v[a];
+    h->P.om[a] = omega[a];
+    h->P.ctr[a] = center[a];
+    moving = moving || v[a] != 0.0 || omega[a] != 0.0;
+  }
+  h->dynamic_r = moving;
+  hipLaunchKernelGGL(k_set_motion_time, dim3(1), dim3(1), 0, h->stream, h->sc);
+  return check_launch();
+}
+
+static void enqueue_step(rbdi_handle* h) {
+  if (h->P.seed != RBDI_SEED_NONE) {
+    if (!h->band_valid || h->dynamic_r) {
+      h->ops->band(h);
+      h->band_valid = true;
+    }
+    h->ops->seed(h);
+  }
+  h->ops->stages(h);
+  hipLaunchKernelGGL(k_end_step, dim3(1), dim3(1), 0, h->stream, h->sc);
+}
+
+RBDI_API int rbdi_step(rbdi_handle* h, double dt) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBDI_ERR_BAD_ARG, "dt must be positive and finite");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, h->stream, h->sc, dt);
+  enqueue_step(h);
+  return check_launch();
+}
+
+RBDI_API int rbdi_compute_dt(rbdi_handle* h, double cfl, double* dt) {
+  if (!h || !dt) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!(cfl > 0.0)) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->dt_partial(h);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, kRedBlocks, cfl, 0.0,
+                     h->sc, h->red_out);
+  HIP_OK(hipMemcpyAsync(dt, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  int rc = check_launch();
+  if (rc) return rc;
+  if (!std::isfinite(*dt) || !(*dt > 0.0) || *dt > 1e299) return fail(RBDI_ERR_NONPHYSICAL, "no finite CFL time step");
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (!(cfl > 0.0) || nsteps < 0) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 and nsteps >= 0");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  for (int s = 0; s < nsteps; ++s) {
+    h->ops->dt_partial(h);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, kRedBlocks, cfl, t_end,
+                       h->sc, (double*)nullptr);
+    enqueue_step(h);
+  }
+  return check_launch();
+}
+
+RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  h->timing = enable != 0;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches) {
+  if (!h || !ms || !launches) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  HIP_OK(hipStreamSynchronize(h->stream));
+  for (size_t k = 0; k < h->ev_used; ++k) {
+    float e = 0.0f;
+    HIP_OK(hipEventElapsedTime(&e, h->ev[2 * k], h->ev[2 * k + 1]));
+    const int c = h->ev_cls[k];
+    ms[c] += e;
+    launches[c] += 1;
+  }
+  h->ev_used = 0;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st) {
+  if (!h || !st) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  DevScalars s{};
+  HIP_OK(hipMemcpyAsync(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  st->steps = s.steps;
+  st->t = s.t;
+  st->last_dt = s.last_dt;
+  st->band_cells = s.band_cells;
+  st->seeded = s.seeded;
+  st->probe_fail = s.probe_fail;
+  st->nonphysical = s.nonphys;
+  st->first_bad = s.nonphys ? s.first_bad : -1;
+  int rc = check_launch();
+  if (rc) return rc;
+  if (s.nonphys) return fail(RBDI_ERR_NONPHYSICAL, "a cell left the admissible set");
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_rigid_force(rbdi_handle* h, const double center[3], double F[3], double T[3]) {
+  if (!h || !center || !F || !T) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->force(h, center);
+  double out[6];
+  HIP_OK(hipMemcpyAsync(out, h->red_out, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  for (int a = 0; a < 3; ++a) { F[a] = out[a]; T[a] = out[3 + a]; }
+  return check_launch();
+}
+
+RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out) {
+  if (!h || !out) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->totals(h);
+  HIP_OK(hipMemcpyAsync(out, h->red_out, sizeof(double) * 2 * h->nf, hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return check_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,654 @@
+// rbdi_kernels.hpp -- gfx950 kernels of the diffuse-interface rigid-body
+// step (arXiv 2111.11806): direction sweeps of the semi-discrete operator with
+// the SSP-RK3 combine fused into the last sweep (Sec. 3.1), rigid-band
+// compaction and interface seeding (Sec. 3.2), the CFL reduction (Sec. 3),
+// FP64 force/torque and conservation reductions, and state conversions.
+//
+// Storage: structure of arrays over interior cells, field q at base + q*fs,
+// cell (i,j,k) at i + j*nx + k*nx*ny. Domain ghost cells are not stored:
+// a load outside the domain maps to its boundary source on the fly.
+//
+// Sweep mapping: one wavefront (64 lanes) owns 64 consecutive cells along the
+// sweep direction, of which the middle 58 are updated (3-cell halo each
+// side, the width of the MUSCL-BVD-THINC stencil). Neighbour values travel by
+// cross-lane shuffles: each cell's closure, reconstruction candidates and
+// face flux are computed once.
+#pragma once
+
+#include "rbdi_physics.hpp"
+
+namespace rbdi {
+
+constexpr int kWave = 64;
+constexpr int kOut = 58;       // cells updated per wavefront
+constexpr int kHalo = 3;
+constexpr int kWPB = 4;        // wavefronts per block in 2D/3D sweeps
+
+// Device-resident scalars of one instance.
+struct DevScalars {
+  double dt;          // dt of the step being executed
+  double t;           // time at the start of the step
+  double t_motion;    // time at which the rigid centre was set
+  double last_dt;
+  long long steps;
+  long long band_cells;
+  long long seeded;
+  long long probe_fail;
+  long long first_bad;
+  int nonphys;
+  int band_count;
+};
+
+template <typename T>
+__device__ inline T shup(T v) { return __shfl_up(v, 1); }
+template <typename T>
+__device__ inline T shdn(T v) { return __shfl_down(v, 1); }
+
+__device__ inline long long cell_index(const Params& P, int i, int j, int k) {
+  return (long long)i * P.st[0] + (long long)j * P.st[1] + (long long)k * P.st[2];
+}
+
+// Boundary mapping of a position along direction d. Returns 0 (use the source
+// cell as is), 1 (mirror: negate the normal velocity and the normal-
+// tangential stretch components) or 2 (Dirichlet state of the face).
+__device__ inline int ghost_map(const Params& P, int d, int pos, int& src, int& face) {
+  const int n = P.n[d];
+  if (pos >= 0 && pos < n) { src = pos; face = -1; return 0; }
+  const int side = pos < 0 ? 0 : 1;
+  face = 2 * d + side;
+  switch (P.bc[face]) {
+    case BC_REFLECTIVE: src = side ? 2 * n - 1 - pos : -1 - pos; return 1;
+    case BC_PERIODIC: src = ((pos % n) + n) % n; return 0;
+    case BC_DIRICHLET: src = 0; return 2;
+    default: src = side ? n - 1 : 0; return 0;
+  }
+}
+
+template <class S, typename T>
+__device__ inline void load_cons(const Params& P, const T* __restrict__ U, long long c, T* Uc) {
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Uc[q] = U[q * P.fs + c];
+}
+
+// Primitive state at (i,j,k) where the coordinate along DIR may lie in the
+// ghost range.
+template <class S, typename T, int DIR>
+__device__ inline void load_prim(const Params& P, const T* __restrict__ U, int i, int j, int k, T* W) {
+  int p[3] = {i, j, k};
+  int src, face;
+  const int mode = ghost_map(P, DIR, p[DIR], src, face);
+  if (mode == 2) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) W[q] = (T)P.bcW[face][q];
+    return;
+  }
+  p[DIR] = src;
+  T Uc[S::NF];
+  load_cons<S>(P, U, cell_index(P, p[0], p[1], p[2]), Uc);
+  cons_to_prim<S>(P, Uc, W);
+  if (mode == 1) {
+    W[S::wU(DIR)] = -W[S::wU(DIR)];
+    if constexpr (S::S) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if ((a == DIR) != (b == DIR)) W[S::wV(a, b)] = -W[S::wV(a, b)];
+    }
+  }
+}
+
+// r at a face-neighbour of an interior cell (ghosts by the boundary map).
+template <class S, typename T>
+__device__ inline double r_at(const Params& P, const T* __restrict__ U, int i, int j, int k, int d, int off) {
+  int p[3] = {i, j, k};
+  int src, face;
+  const int mode = ghost_map(P, d, p[d] + off, src, face);
+  if (mode == 2) return P.bcW[face][S::R];
+  p[d] = src;
+  return (double)U[S::R * P.fs + cell_index(P, p[0], p[1], p[2])];
+}
+
+// ---------------------------------------------------------------------------
+// Direction sweep of one RK stage.
+// MODE 0: write this direction's contribution to D; 1: add it to D;
+// 2: final sweep -- total D, RK combine U_out = U^n + b (U_in - dt D - U^n)
+//    (b = 1, 1/4, 2/3; Sec. 3.1), rigid freeze, solid sources, admissibility.
+// ---------------------------------------------------------------------------
+template <class S, typename T, int DIR, int MODE>
+__global__ __launch_bounds__(256) void k_sweep(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
+                                              T* __restrict__ Dacc, T* __restrict__ Uout,
+                                              DevScalars* __restrict__ sc, double bcoef, int stage) {
+  const double dt = sc->dt;
+  if (dt == 0.0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  int i, j, k, seg;
+  if (DIR == 0) { seg = blockIdx.x; j = blockIdx.y * wpb + wave; k = blockIdx.z; i = 0; if (j >= P.n[1]) return; }
+  else if (DIR == 1) { i = blockIdx.x * wpb + wave; seg = blockIdx.y; k = blockIdx.z; j = 0; if (i >= P.n[0]) return; }
+  else { i = blockIdx.x * wpb + wave; j = blockIdx.y; seg = blockIdx.z; k = 0; if (i >= P.n[0]) return; }
+  const int nd = P.n[DIR];
+  const int pos = seg * kOut - kHalo + lane;
+  const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
+  int pc[3] = {i, j, k};
+  pc[DIR] = posl;
+
+  T W[S::NF];
+  load_prim<S, T, DIR>(P, Uin, pc[0], pc[1], pc[2], W);
+
+  // MUSCL-BVD-THINC per variable (Sec. 3.1)
+  T sL[S::NF], sR[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) {
+    const T wm = shup(W[q]), wp = shdn(W[q]);
+    const Cand<T> c = candidates(P, wm, W[q], wp);
+    const T lmR = shup(c.mR), ltR = shup(c.tR);
+    const T rmL = shdn(c.mL), rtL = shdn(c.tL);
+    bvd(P, lmR, ltR, c, rmL, rtL, sL[q], sR[q]);
+  }
+  if (!admissible<S>(P, sL) || !admissible<S>(P, sR)) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) { sL[q] = W[q]; sR[q] = W[q]; }
+  }
+  // face pos+1/2: left state = this cell's right face, right state = the
+  // next cell's left face
+  T WR[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) WR[q] = shdn(sL[q]);
+  T F[S::NT], us, Vs[3] = {T(0), T(0), T(0)};
+  hllc<S, DIR>(P, sR, WR, F, us, Vs);
+  // rigid velocity at the face and the upwind r flux (Sec. 3.1)
+  double xf[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xf[a] = a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0;
+  xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR];
+  double vface;
+  {
+    double xs[3];
+    const double tc = sc->t - sc->t_motion;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xs[a] = xf[a] - P.vr[a] * tc;  // position relative to the moving centre
+    double v[3];
+    rigid_velocity(P, xs, v);
+    vface = v[DIR];
+  }
+  const T vf = (T)vface;
+  const T rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
+
+  // left face of this cell from the previous lane
+  T Fm[S::NT];
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) Fm[q] = shup(F[q]);
+  const T usm = shup(us), vfm = shup(vf), rflm = shup(rfl);
+  T Vsm[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) Vsm[b] = shup(Vs[b]);
+
+  const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
+  if (!outlane) return;
+  const T inv = (T)P.inv_dx[DIR];
+  T d[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) d[q] = (F[q] - Fm[q]) * inv;
+  const T du = us - usm;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) d[S::cPHI(l)] -= W[S::wPHI(l)] * du * inv;
+  if constexpr (S::S) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T ua = a < S::D ? W[S::wU(a)] : T(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        d[S::cV(a, b)] -= (T(2.0 / 3.0) * W[S::wV(a, b)] * du - ua * (Vs[b] - Vsm[b])) * inv;
+    }
+  }
+  d[S::R] = ((rfl - rflm) - W[S::R] * (vf - vfm)) * inv;
+
+  const long long c = cell_index(P, pc[0], pc[1], pc[2]);
+  if (MODE == 0) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Dacc[q * P.fs + c] = d[q];
+    return;
+  }
+  if (MODE == 1) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Dacc[q * P.fs + c] += d[q];
+    return;
+  }
+  if (S::D > 1) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) d[q] = Dacc[q * P.fs + c] + d[q];
+  }
+  const T dtt = (T)dt;
+  const T b = (T)bcoef;
+  const bool rigid = (double)U0[S::R * P.fs + c] > 0.5;
+  T Un[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) {
+    const T ui = Uin[q * P.fs + c];
+    const T ust = ui - dtt * d[q];
+    if (stage == 0) {
+      Un[q] = (rigid && q != S::R) ? ui : ust;
+    } else {
+      const T u0 = U0[q * P.fs + c];
+      Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
+    }
+  }
+  if constexpr (S::S) {
+    if (!rigid) solid_sources<S>(P, Un);
+  }
+  bool ok = true;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) ok = ok && (Un[S::cA(l)] > T(0));
+  ok = ok && isfinite((double)Un[S::cE]);
+  if (!ok) {
+    if (atomicExch(&sc->nonphys, 1) == 0) sc->first_bad = c;
+  }
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = Un[q];
+}
+
+// ---------------------------------------------------------------------------
+// Rigid band (rigid cells with a nonzero r gradient) and seeding (Sec. 3.2)
+// ---------------------------------------------------------------------------
+
+__device__ inline void decode(const Params& P, long long c, int& i, int& j, int& k) {
+  i = (int)(c % P.n[0]);
+  j = (int)((c / P.n[0]) % P.n[1]);
+  k = (int)(c / ((long long)P.n[0] * P.n[1]));
+}
+
+// Youngs normal (Sec. 3.3): n = -grad r / |grad r| with central differences.
+template <class S, typename T>
+__device__ inline bool youngs_normal(const Params& P, const T* __restrict__ U, int i, int j, int k, double n[3]) {
+  double g[3] = {0.0, 0.0, 0.0}, m2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < S::D; ++d) {
+    g[d] = (r_at<S>(P, U, i, j, k, d, 1) - r_at<S>(P, U, i, j, k, d, -1)) / (2.0 * P.dx[d]);
+    m2 += g[d] * g[d];
+  }
+  const double mag = sqrt(m2);
+  if (!(mag * P.dmin > 1e-12)) return false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) n[d] = d < S::D ? -g[d] / mag : 0.0;
+  return true;
+}
+
+template <class S, typename T>
+__global__ __launch_bounds__(256) void k_band(Params P, const T* __restrict__ U, int* __restrict__ band,
+                                             DevScalars* __restrict__ sc) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell || sc->dt == 0.0) return;
+  if (!((double)U[S::R * P.fs + c] > 0.5)) return;
+  int i, j, k;
+  decode(P, c, i, j, k);
+  double n[3];
+  if (!youngs_normal<S>(P, U, i, j, k, n)) return;
+  const int slot = atomicAdd(&sc->band_count, 1);
+  band[slot] = (int)c;
+}
+
+// Seeding of every band cell: probe along n at 1, 1.5, ..., 4 dx (or the
+// fixed 1.5 dx), first point whose nonzero-weight enclosing cells are all
+// interior with r <= 0.5, multilinear interpolation of primitives (nested
+// linear interpolations), mirror state, optional Riemann star state, write
+// the thermodynamic fields. Support cells are never rigid, so cells seeded
+// by other threads are never read.
+template <class S, typename T>
+__global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const int* __restrict__ band,
+                                             DevScalars* __restrict__ sc) {
+  if (sc->dt == 0.0) return;  // a step after t_end does no work
+  const int nb = sc->band_count;
+  int nfail = 0, nseed = 0;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const long long c = band[b];
+    int pi[3];
+    decode(P, c, pi[0], pi[1], pi[2]);
+    double n[3];
+    if (!youngs_normal<S>(P, U, pi[0], pi[1], pi[2], n)) continue;
+    const int nprobe = P.probe == PROBE_FIXED ? 1 : 7;
+    int lo[3] = {0, 0, 0};
+    double w[3] = {0.0, 0.0, 0.0};
+    bool found = false;
+    for (int pr = 0; pr < nprobe && !found; ++pr) {
+      const double dist = P.probe == PROBE_FIXED ? 1.5 : 1.0 + 0.5 * pr;
+#pragma unroll
+      for (int a = 0; a < S::D; ++a) {
+        const double xi = pi[a] + dist * n[a] * (P.dmin * P.inv_dx[a]);
+        lo[a] = (int)floor(xi);
+        w[a] = xi - lo[a];
+      }
+      bool ok = true;
+#pragma unroll
+      for (int cb = 0; cb < (1 << S::D); ++cb) {
+        int cp[3] = {0, 0, 0};
+        bool used = true;
+#pragma unroll
+        for (int a = 0; a < S::D; ++a) {
+          const int bit = (cb >> a) & 1;
+          if (bit && w[a] == 0.0) used = false;
+          cp[a] = lo[a] + bit;
+        }
+        if (!used || !ok) continue;
+#pragma unroll
+        for (int a = 0; a < S::D; ++a) ok = ok && cp[a] >= 0 && cp[a] < P.n[a];
+        if (ok) ok = (double)U[S::R * P.fs + cell_index(P, cp[0], cp[1], cp[2])] <= 0.5;
+      }
+      found = ok;
+    }
+    if (!found) { ++nfail; continue; }
+    // primitives at the support corners
+    double Wc[1 << S::D][S::NF];
+#pragma unroll
+    for (int cb = 0; cb < (1 << S::D); ++cb) {
+      int cp[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < S::D; ++a) {
+        const int bit = (cb >> a) & 1;
+        cp[a] = lo[a] + ((bit && w[a] != 0.0) ? 1 : 0);
+      }
+      T Uc[S::NF], Wt[S::NF];
+      load_cons<S>(P, U, cell_index(P, cp[0], cp[1], cp[2]), Uc);
+      cons_to_prim<S>(P, Uc, Wt);
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) Wc[cb][q] = (double)Wt[q];
+    }
+    int m = 1 << S::D;
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) {
+      m >>= 1;
+      for (int cb = 0; cb < m; ++cb)
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q)
+          Wc[cb][q] = Wc[2 * cb][q] + w[a] * (Wc[2 * cb + 1][q] - Wc[2 * cb][q]);
+    }
+    double xc[3] = {0.0, 0.0, 0.0};
+    const double tc = sc->t - sc->t_motion;
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) xc[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xc[a] -= P.vr[a] * tc;
+    double v[3];
+    rigid_velocity(P, xc, v);
+    double Wm[S::NF], Wg[S::NF];
+    mirror<S>(Wc[0], n, v, Wm);
+    if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], n, Wg);
+    else {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) Wg[q] = Wm[q];
+    }
+    T Wt[S::NF], Ug[S::NF];
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Wt[q] = (T)Wg[q];
+    Wt[S::R] = U[S::R * P.fs + c];
+    prim_to_cons<S>(P, Wt, Ug);
+#pragma unroll
+    for (int q = 0; q < S::NT; ++q) U[q * P.fs + c] = Ug[q];
+    ++nseed;
+  }
+  if (nfail) atomicAdd((unsigned long long*)&sc->probe_fail, (unsigned long long)nfail);
+  if (nseed) atomicAdd((unsigned long long*)&sc->seeded, (unsigned long long)nseed);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (fixed grid, fixed-order trees: deterministic)
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__device__ inline T block_min(T v, T* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) v = fmin(v, sh[q]);
+    sh[0] = v;
+  }
+  __syncthreads();
+  v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// Fixed-order block sum of one double per thread (pairwise tree in LDS).
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// CFL candidate of each non-rigid cell: min_d dx_d / max(|u_d| + c, |v_r,d|).
+template <class S, typename T>
+__global__ __launch_bounds__(kRedThreads) void k_dt_partial(Params P, const T* __restrict__ U,
+                                                           const DevScalars* __restrict__ sc,
+                                                           double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  double m = 1e300;
+  const double tc = sc->t - sc->t_motion;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    if ((double)U[S::R * P.fs + c] > 0.5) continue;
+    T Uc[S::NF], W[S::NF];
+    load_cons<S>(P, U, c, Uc);
+    double J2 = 0.0;
+    cons_to_prim<S>(P, Uc, W, nullptr, &J2);
+    double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
+    phases_w<S>(W, phi, rl);
+    mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
+    const double cs = sqrt(c2);
+    int pi[3];
+    decode(P, c, pi[0], pi[1], pi[2]);
+    double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] -= P.vr[a] * tc;
+    double v[3];
+    rigid_velocity(P, x, v);
+#pragma unroll
+    for (int d = 0; d < S::D; ++d) {
+      const double s = fmax(fabs((double)W[S::wU(d)]) + cs, fabs(v[d]));
+      m = fmin(m, P.dx[d] / s);
+    }
+  }
+  m = block_min(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// dt = cfl * min, clipped at t_end (t_end <= 0: no clip); dt = 0 once t_end
+// is reached (the step then does no work).
+__global__ void k_dt_final(const double* __restrict__ part, int nparts, double cfl, double t_end,
+                           DevScalars* __restrict__ sc, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double m = 1e300;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) m = fmin(m, part[q]);
+  m = block_min(m, sh);
+  if (threadIdx.x == 0) {
+    double dt = cfl * m;
+    if (t_end > 0.0) {
+      const double rem = t_end - sc->t;
+      if (!(rem > 1e-14 * t_end)) dt = 0.0;
+      else if (dt > rem) dt = rem;
+    }
+    if (out) *out = dt;
+    else sc->dt = dt;
+  }
+}
+
+__global__ void k_set_dt(DevScalars* sc, double dt) { sc->dt = dt; }
+
+__global__ void k_end_step(DevScalars* sc) {
+  const double dt = sc->dt;
+  if (dt == 0.0) return;
+  sc->t += dt;
+  sc->last_dt = dt;
+  sc->steps += 1;
+}
+
+__global__ void k_reset_band(DevScalars* sc) {
+  if (sc->dt != 0.0) sc->band_count = 0;
+}
+__global__ void k_band_stat(DevScalars* sc) {
+  if (sc->dt != 0.0) sc->band_cells = sc->band_count;
+}
+
+// Force and torque: per cell f = -sigma . grad_h r dV, torque (x - c) x f.
+template <class S, typename T>
+__global__ __launch_bounds__(kRedThreads) void k_force_partial(Params P, const T* __restrict__ U, double cx,
+                                                              double cy, double cz, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double dV = 1.0;
+  for (int d = 0; d < S::D; ++d) dV *= P.dx[d];
+  const double ctr[3] = {cx, cy, cz};
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    int pi[3];
+    decode(P, c, pi[0], pi[1], pi[2]);
+    double g[3] = {0.0, 0.0, 0.0};
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < S::D; ++d) {
+      g[d] = (r_at<S>(P, U, pi[0], pi[1], pi[2], d, 1) - r_at<S>(P, U, pi[0], pi[1], pi[2], d, -1)) /
+             (2.0 * P.dx[d]);
+      any = any || g[d] != 0.0;
+    }
+    if (!any) continue;
+    T Uc[S::NF], W[S::NF];
+    load_cons<S>(P, U, c, Uc);
+    double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, J2 = 0.0;
+    cons_to_prim<S>(P, Uc, W, H, &J2);
+    double G = 0.0;
+    if constexpr (S::S) {
+      double phi[kMaxMat], rl[kMaxMat], c2, sY;
+      phases_w<S>(W, phi, rl);
+      mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
+    }
+    const double p = (double)W[S::wP];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double sig = (a == b ? -p : 0.0) + 2.0 * G * H[3 * a + b];
+        s -= sig * g[b];
+      }
+      f[a] = s * dV;
+    }
+    double xr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) xr[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a] - ctr[a];
+    acc[0] += f[0];
+    acc[1] += f[1];
+    acc[2] += f[2];
+    acc[3] += xr[1] * f[2] - xr[2] * f[1];
+    acc[4] += xr[2] * f[0] - xr[0] * f[2];
+    acc[5] += xr[0] * f[1] - xr[1] * f[0];
+  }
+  for (int q = 0; q < 6; ++q) {
+    const double s = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Totals of every field (all cells, non-rigid cells), times dV.
+template <class S, typename T>
+__global__ __launch_bounds__(kRedThreads) void k_totals_partial(Params P, const T* __restrict__ U,
+                                                               double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  double all[S::NF], flu[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) { all[q] = 0.0; flu[q] = 0.0; }
+  double dV = 1.0;
+  for (int d = 0; d < S::D; ++d) dV *= P.dx[d];
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    const bool rig = (double)U[S::R * P.fs + c] > 0.5;
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) {
+      const double v = (double)U[q * P.fs + c] * dV;
+      all[q] += v;
+      flu[q] += rig ? 0.0 : v;
+    }
+  }
+  for (int q = 0; q < S::NF; ++q) {
+    double s = block_sum(all[q], sh);
+    if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = s;
+    s = block_sum(flu[q], sh);
+    if (threadIdx.x == 0) part[(S::NF + q) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Final fixed-order sum of nq rows of nparts partials.
+__global__ void k_sum_rows(const double* __restrict__ part, int nparts, int nq, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) v += part[q * nparts + b];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) out[q] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Conversions and initialisation
+// ---------------------------------------------------------------------------
+
+template <class S, typename T>
+__global__ void k_prim_to_state(Params P, const double* __restrict__ Win, T* __restrict__ U) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  T W[S::NF], Uc[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) W[q] = (T)Win[q * P.ncell + c];
+  prim_to_cons<S>(P, W, Uc);
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) U[q * P.fs + c] = Uc[q];
+}
+
+template <class S, typename T>
+__global__ void k_state_to_prim(Params P, const T* __restrict__ U, double* __restrict__ Wout) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  T Uc[S::NF], W[S::NF];
+  load_cons<S>(P, U, c, Uc);
+  cons_to_prim<S>(P, Uc, W);
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Wout[q * P.ncell + c] = (double)W[q];
+}
+
+template <class S, typename T>
+__global__ void k_state_to_f64(Params P, const T* __restrict__ U, double* __restrict__ out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) out[q * P.ncell + c] = (double)U[q * P.fs + c];
+}
+
+template <class S, typename T>
+__global__ void k_f64_to_state(Params P, const double* __restrict__ in, T* __restrict__ U) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) U[q * P.fs + c] = (T)in[q * P.ncell + c];
+}
+
+// r = (1 - tanh(sdf / (width dx_min))) / 2 (bodies as a diffuse scalar field).
+template <class S, typename T>
+__global__ void k_r_from_sdf(Params P, const double* __restrict__ sdf, double inv_w, T* __restrict__ U) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  U[S::R * P.fs + c] = (T)(0.5 * (1.0 - tanh(sdf[c] * inv_w)));
+}
+
+}  // namespace rbdi

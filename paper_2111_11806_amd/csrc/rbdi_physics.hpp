@@ -1,0 +1,753 @@
+// rbdi_physics.hpp -- device physics of the diffuse-interface rigid-body
+// method (arXiv 2111.11806) for gfx950: field layout, mixture closure,
+// MUSCL-BVD-THINC candidates, HLLC / HLLC-LM flux, mirror and Riemann
+// seeding states, stretch-tensor algebra and the plastic return.
+//
+// Everything here is per cell or per face and lives in registers; the
+// kernels that move data are in rbdi_kernels.hpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rbdi {
+
+constexpr int kMaxF = 20;
+constexpr int kMaxMat = 2;
+
+enum { EOS_IDEAL = 0, EOS_STIFFENED = 1, EOS_ROMENSKII = 2 };
+enum { BC_TRANSMISSIVE = 0, BC_REFLECTIVE = 1, BC_DIRICHLET = 2, BC_PERIODIC = 3 };
+enum { REC_MUSCL = 0, REC_BVD_THINC = 1 };
+enum { RS_HLLC = 0, RS_HLLC_LM = 1 };
+enum { SEED_ORIGINAL = 0, SEED_RIEMANN = 1, SEED_NONE = 2 };
+enum { PROBE_STEPOUT = 0, PROBE_FIXED = 1 };
+
+// Material constants in the form the device closure uses.
+struct MatDev {
+  int kind;
+  double gamma, pinf;
+  double Gam, invGam;   // Gruneisen coefficient and its inverse
+  double Bfl;           // fluids: rho e_ref - p_ref / Gamma = gamma p_inf / Gamma
+  double rho0, invrho0, K0, G0, alpha, beta, kc;  // Romenskii, kc = K0 / (2 alpha^2)
+  double sigY;
+};
+
+// Launch-invariant parameters of one instance (passed by value).
+struct Params {
+  int dim;
+  int n[3];
+  long long st[3];        // element strides of x, y, z
+  long long fs;           // element stride between fields
+  long long ncell;        // interior cells
+  double dx[3], inv_dx[3], x0[3], dmin;
+  int bc[6];
+  int recon, riemann, seed, probe, plastic;
+  double cosh_b, inv_sinh_b, tanh_b, beta;
+  double lm_mach;
+  int solid_phase;
+  MatDev mat[kMaxMat];
+  double vr[3], om[3], ctr[3];
+  double bcW[6][kMaxF];   // Dirichlet primitive states per face
+};
+
+// Compile-time field layout of the reduced-equation multi-material system
+// (Sec. 2.1.1, 2.4):
+//   U = (phi_l rho_l [N], rho u [D], rho E, phi_l [N-1], Vbar [9], a_s eps_p, r)
+//   W = (phi_l [N-1], rho_l [N], u [D], p, Vbar [9], eps_p, r)
+template <int DIM_, int NMAT_, bool SOLID_>
+struct Sys {
+  static constexpr int D = DIM_;
+  static constexpr int N = NMAT_;
+  static constexpr bool S = SOLID_;
+  static constexpr int NF = 2 * N + D + 1 + (S ? 10 : 0);
+  static constexpr int NT = NF - 1;  // thermodynamic fields
+  static constexpr int R = NF - 1;
+  __host__ __device__ static constexpr int cA(int l) { return l; }
+  __host__ __device__ static constexpr int cM(int a) { return N + a; }
+  static constexpr int cE = N + D;
+  __host__ __device__ static constexpr int cPHI(int l) { return N + D + 1 + l; }
+  __host__ __device__ static constexpr int cV(int a, int b) { return 2 * N + D + 3 * a + b; }
+  static constexpr int cEP = 2 * N + D + 9;
+  __host__ __device__ static constexpr int wPHI(int l) { return l; }
+  __host__ __device__ static constexpr int wRHO(int l) { return N - 1 + l; }
+  __host__ __device__ static constexpr int wU(int a) { return 2 * N - 1 + a; }
+  static constexpr int wP = 2 * N - 1 + D;
+  __host__ __device__ static constexpr int wV(int a, int b) { return 2 * N + D + 3 * a + b; }
+  static constexpr int wEP = 2 * N + D + 9;
+};
+
+// ---------------------------------------------------------------------------
+// Small 3x3 algebra (stretch tensor)
+// ---------------------------------------------------------------------------
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations with a fixed
+// maximum number of sweeps and an early exit once the off-diagonal part is
+// below roundoff of the diagonal.
+template <typename T>
+__device__ inline void jacobi3(T A[3][3], T Q[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Q[i][j] = (i == j) ? T(1) : T(0);
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const T dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= T(1e-34) * dg || off == T(0)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const T apq = A[p][q];
+      if (apq == T(0)) continue;
+      const T th = (A[q][q] - A[p][p]) / (T(2) * apq);
+      const T t = (th >= T(0) ? T(1) : T(-1)) / (fabs(th) + sqrt(th * th + T(1)));
+      const T c = T(1) / sqrt(t * t + T(1));
+      const T s = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T akp = A[k][p], akq = A[k][q];
+        A[k][p] = c * akp - s * akq;
+        A[k][q] = s * akp + c * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T apk = A[p][k], aqk = A[q][k];
+        A[p][k] = c * apk - s * aqk;
+        A[q][k] = s * apk + c * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T qkp = Q[k][p], qkq = Q[k][q];
+        Q[k][p] = c * qkp - s * qkq;
+        Q[k][q] = s * qkp + c * qkq;
+      }
+    }
+  }
+}
+
+// Hencky strain H = (1/2) ln(Vbar Vbar^T) (equals ln Vbar for a symmetric
+// stretch; Sec. 2.1.2) and J2 = H:H.
+template <typename T>
+__device__ inline void hencky3(const T V[9], T H[9], T& J2) {
+  T b[3][3], Q[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      b[i][j] = V[3 * i] * V[3 * j] + V[3 * i + 1] * V[3 * j + 1] + V[3 * i + 2] * V[3 * j + 2];
+  jacobi3(b, Q);
+  T h[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) h[k] = T(0.5) * log(b[k][k]);
+  J2 = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T v = Q[i][0] * h[0] * Q[j][0] + Q[i][1] * h[1] * Q[j][1] + Q[i][2] * h[2] * Q[j][2];
+      H[3 * i + j] = v;
+      J2 += v * v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Closure (Sec. 2.1.2 Mie-Gruneisen form, Sec. 2.1.3 EOS, Sec. 2.2 mixture)
+// ---------------------------------------------------------------------------
+
+// Per-phase reference terms: B = rho e_ref - p_ref / Gamma (enters the
+// isobaric pressure inversion), the phase sound speed squared, and the shear
+// modulus. Fluids (ideal / stiffened): B = gamma p_inf / Gamma, c^2 =
+// gamma (p + p_inf) / rho, G = 0. Romenskii: x = rho/rho0, y = x^alpha,
+// G = G0 x^(beta+1), rho e_ref = kc (y-1)^2 + G J2,
+// p_ref = kc (y-1)((2 alpha - 1) y + 1) + beta G J2,
+// a^2 = (Gamma + 1)(p - p_ref)/rho + dp_ref/drho, c^2 = a^2 + 4 G / (3 rho).
+struct PhaseOut {
+  double B, c2, G;
+};
+
+__device__ inline void romenskii_ref(const MatDev& m, double rho, double J2, double& rhoe_ref,
+                                     double& p_ref, double& dpref, double& G) {
+  const double x = rho * m.invrho0;
+  const double y = (m.alpha == 1.0) ? x : pow(x, m.alpha);
+  G = m.G0 * pow(x, m.beta + 1.0);
+  const double ym = y - 1.0;
+  rhoe_ref = m.kc * ym * ym + G * J2;
+  p_ref = m.kc * ym * ((2.0 * m.alpha - 1.0) * y + 1.0) + m.beta * G * J2;
+  dpref = (m.K0 / m.alpha) * ((2.0 * m.alpha - 1.0) * y - m.alpha + 1.0) * y / rho +
+          m.beta * (m.beta + 1.0) * G * J2 / rho;
+}
+
+// Mixture pressure from rho e (FP64 in every precision):
+// p = [rho e - sum phi_l B_l] / sum(phi_l / Gamma_l).
+template <class S>
+__device__ inline double mix_pressure(const Params& P, const double* phi, const double* rho, double J2,
+                                      double rhoe) {
+  double num = rhoe, den = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const MatDev& m = P.mat[l];
+    double B = m.Bfl;
+    if (S::S && m.kind == EOS_ROMENSKII) {
+      double er, pr, dp, G;
+      romenskii_ref(m, rho[l], J2, er, pr, dp, G);
+      B = er - pr * m.invGam;
+    }
+    num -= phi[l] * B;
+    den += phi[l] * m.invGam;
+  }
+  return num / den;
+}
+
+// rho e from p (the same isobaric relation solved for rho e).
+template <class S>
+__device__ inline double mix_rhoe(const Params& P, const double* phi, const double* rho, double J2, double p) {
+  double s = 0.0, den = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const MatDev& m = P.mat[l];
+    double B = m.Bfl;
+    if (S::S && m.kind == EOS_ROMENSKII) {
+      double er, pr, dp, G;
+      romenskii_ref(m, rho[l], J2, er, pr, dp, G);
+      B = er - pr * m.invGam;
+    }
+    s += phi[l] * B;
+    den += phi[l] * m.invGam;
+  }
+  return p * den + s;
+}
+
+// Mixture sound speed squared (Sec. 2.2, mass-fraction weighted over
+// sum phi/Gamma), shear modulus (Sec. 2.2) and yield stress (same weights).
+template <class S>
+__device__ inline void mix_c2_G(const Params& P, const double* phi, const double* rho, double J2, double p,
+                                double& c2, double& G, double& sigY) {
+  double rhom = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) rhom += phi[l] * rho[l];
+  double nc = 0.0, nG = 0.0, nY = 0.0, den = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const MatDev& m = P.mat[l];
+    double cl2, Gl = 0.0;
+    if (S::S && m.kind == EOS_ROMENSKII) {
+      double er, pr, dp;
+      romenskii_ref(m, rho[l], J2, er, pr, dp, Gl);
+      cl2 = (m.Gam + 1.0) * (p - pr) / rho[l] + dp + (4.0 / 3.0) * Gl / rho[l];
+    } else {
+      cl2 = m.gamma * (p + m.pinf) / rho[l];
+    }
+    nc += phi[l] * rho[l] * cl2 * m.invGam;
+    nG += phi[l] * Gl * m.invGam;
+    nY += phi[l] * m.sigY * m.invGam;
+    den += phi[l] * m.invGam;
+  }
+  const double inv = 1.0 / den;
+  c2 = nc / rhom * inv;
+  G = nG * inv;
+  sigY = nY * inv;
+}
+
+// Volume fractions and phasic densities of a primitive vector.
+template <class S, typename T>
+__device__ inline void phases_w(const T* W, double* phi, double* rho) {
+  double s = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) {
+    phi[l] = (double)W[S::wPHI(l)];
+    s += phi[l];
+  }
+  phi[S::N - 1] = 1.0 - s;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) rho[l] = (double)W[S::wRHO(l)];
+}
+
+// Conserved -> primitive (Sec. 2.2). For the elastoplastic system the
+// Hencky strain of Vbar is also returned (J2, H).
+template <class S, typename T>
+__device__ inline void cons_to_prim(const Params& P, const T* U, T* W, double* Hout = nullptr,
+                                    double* J2out = nullptr) {
+  double rho = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) rho += (double)U[S::cA(l)];
+  double phi[kMaxMat], rl[kMaxMat];
+  double s = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) {
+    phi[l] = (double)U[S::cPHI(l)];
+    s += phi[l];
+  }
+  phi[S::N - 1] = 1.0 - s;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) rl[l] = (double)U[S::cA(l)] / phi[l];
+  const double inv = 1.0 / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) {
+    const double u = (double)U[S::cM(a)] * inv;
+    W[S::wU(a)] = (T)u;
+    ke += u * (double)U[S::cM(a)];
+  }
+  const double rhoe = (double)U[S::cE] - 0.5 * ke;
+  double J2 = 0.0;
+  if constexpr (S::S) {
+    double V[9], H[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      V[q] = (double)U[S::cV(0, 0) + q];
+      W[S::wV(0, 0) + q] = U[S::cV(0, 0) + q];
+    }
+    hencky3(V, H, J2);
+    if (Hout) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Hout[q] = H[q];
+    }
+    const int sp = P.solid_phase;
+    W[S::wEP] = (T)((double)U[S::cEP] / (double)U[S::cA(sp)]);
+  }
+  if (J2out) *J2out = J2;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) W[S::wPHI(l)] = U[S::cPHI(l)];
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) W[S::wRHO(l)] = (T)rl[l];
+  W[S::wP] = (T)mix_pressure<S>(P, phi, rl, J2, rhoe);
+  W[S::R] = U[S::R];
+}
+
+// Primitive -> conserved. Returns J2 (and H) of the stretch when solid.
+template <class S, typename T>
+__device__ inline void prim_to_cons(const Params& P, const T* W, T* U, double* Hout = nullptr) {
+  double phi[kMaxMat], rl[kMaxMat];
+  phases_w<S>(W, phi, rl);
+  double rho = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const double a = phi[l] * rl[l];
+    U[S::cA(l)] = (T)a;
+    rho += a;
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) {
+    const double u = (double)W[S::wU(a)];
+    U[S::cM(a)] = (T)(rho * u);
+    ke += rho * u * u;
+  }
+  double J2 = 0.0;
+  if constexpr (S::S) {
+    double V[9], H[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      V[q] = (double)W[S::wV(0, 0) + q];
+      U[S::cV(0, 0) + q] = W[S::wV(0, 0) + q];
+    }
+    hencky3(V, H, J2);
+    if (Hout) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Hout[q] = H[q];
+    }
+    const int sp = P.solid_phase;
+    U[S::cEP] = (T)(phi[sp] * rl[sp] * (double)W[S::wEP]);
+  }
+  U[S::cE] = (T)(mix_rhoe<S>(P, phi, rl, J2, (double)W[S::wP]) + 0.5 * ke);
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) U[S::cPHI(l)] = W[S::wPHI(l)];
+  U[S::R] = W[S::R];
+}
+
+// Admissibility of a reconstructed primitive state (positive phasic
+// densities, volume fractions in [0,1], p + p_inf > 0 for fluid phases).
+template <class S, typename T>
+__device__ inline bool admissible(const Params& P, const T* W) {
+  double phi[kMaxMat], rl[kMaxMat];
+  phases_w<S>(W, phi, rl);
+  const double p = (double)W[S::wP];
+  bool ok = true;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    ok = ok && (rl[l] > 0.0) && (phi[l] >= 0.0) && (phi[l] <= 1.0);
+    if (P.mat[l].kind != EOS_ROMENSKII) ok = ok && (p + P.mat[l].pinf > 0.0);
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction (Sec. 3.1: MUSCL on primitives, THINC, BVD selection)
+// ---------------------------------------------------------------------------
+
+// Candidates of one variable in one cell: {MUSCL left, MUSCL right, THINC
+// left, THINC right}. van Leer slope; THINC where the cell is strictly
+// monotone, with the closed-form face values of the tanh profile whose cell
+// average is the cell value.
+template <typename T>
+struct Cand {
+  T mL, mR, tL, tR;
+};
+
+template <typename T>
+__device__ inline Cand<T> candidates(const Params& P, T qm, T q0, T qp) {
+  Cand<T> c;
+  const T a = qp - q0, b = q0 - qm;
+  const T ab = a * b;
+  T half_slope = T(0);
+  if (ab > T(0)) half_slope = ab / (a + b);
+  c.mL = q0 - half_slope;
+  c.mR = q0 + half_slope;
+  c.tL = c.mL;
+  c.tR = c.mR;
+  if (P.recon == REC_BVD_THINC && ab > T(0)) {
+    const T qmin = qm < qp ? qm : qp;
+    const T dq = fabs(qp - qm);
+    const T th = qp > qm ? T(1) : T(-1);
+    const T C = (q0 - qmin) / dq;
+    const T e = exp(th * T(P.beta) * (T(2) * C - T(1)));
+    const T tt = (T(P.cosh_b) - e) * T(P.inv_sinh_b);
+    const T tb = T(P.tanh_b);
+    const T hd = T(0.5) * dq;
+    c.tL = qmin + hd * (T(1) - th * tt);
+    c.tR = qmin + hd * (T(1) + th * (tb - tt) / (T(1) - tb * tt));
+  }
+  return c;
+}
+
+// BVD (Sec. 3.1): THINC faces when their total boundary variation against
+// the neighbours' faces of the same scheme is strictly smaller.
+template <typename T>
+__device__ inline void bvd(const Params& P, T lmR, T ltR, const Cand<T>& c0, T rmL, T rtL, T& qL, T& qR) {
+  const T tbm = fabs(lmR - c0.mL) + fabs(c0.mR - rmL);
+  const T tbt = fabs(ltR - c0.tL) + fabs(c0.tR - rtL);
+  const bool thinc = (P.recon == REC_BVD_THINC) && (tbt < tbm);
+  qL = thinc ? c0.tL : c0.mL;
+  qR = thinc ? c0.tR : c0.mR;
+}
+
+// ---------------------------------------------------------------------------
+// Riemann solver (Sec. 3.1 HLLC; Sec. 4.3 HLLC-LM)
+// ---------------------------------------------------------------------------
+
+// Side data of a face state along direction d.
+template <class S>
+struct SideState {
+  double rho, un, P, c, E;   // density, normal velocity, normal traction, sound speed, rho E
+  double u[3];
+  double sig[3];             // sigma_{a d}, tension positive
+  double phi[kMaxMat], rl[kMaxMat];
+  double H[9];
+};
+
+template <class S, int DIR, typename T>
+__device__ inline void side_state(const Params& P, const T* W, SideState<S>& s) {
+  phases_w<S>(W, s.phi, s.rl);
+  s.rho = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) s.rho += s.phi[l] * s.rl[l];
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s.u[a] = a < S::D ? (double)W[S::wU(a)] : 0.0;
+    ke += s.u[a] * s.u[a];
+  }
+  s.un = s.u[DIR];
+  const double p = (double)W[S::wP];
+  double J2 = 0.0;
+  if constexpr (S::S) {
+    double V[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) V[q] = (double)W[S::wV(0, 0) + q];
+    hencky3(V, s.H, J2);
+  }
+  double c2, G, sY;
+  mix_c2_G<S>(P, s.phi, s.rl, J2, p, c2, G, sY);
+  s.c = sqrt(c2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double sg = (a == DIR) ? -p : 0.0;
+    if constexpr (S::S) sg += 2.0 * G * s.H[3 * a + DIR];
+    s.sig[a] = sg;
+  }
+  s.P = -s.sig[DIR];
+  s.E = mix_rhoe<S>(P, s.phi, s.rl, J2, p) + 0.5 * s.rho * ke;
+}
+
+// Conserved value, physical flux and star value of field q on one side.
+// chi = (S_K - u_K)/(S_K - S*); star: mass-like fields * chi, normal
+// momentum rho* S*, tangential rho* u_t, energy chi [E + (S*-u)(rho S* +
+// P/(S-u))], phi * chi, Vbar rows scaled by chi^(-2/3) (normal) and
+// chi^(1/3) (tangential).
+template <class S, int DIR, typename T>
+__device__ inline void field_terms(const T* W, const SideState<S>& s, int q, int sp, double Sk, double Ss,
+                                   double chi, double cn, double ct, double& u, double& f, double& us) {
+  const double un = s.un;
+  if (q < S::N) {  // phi_l rho_l
+    u = s.phi[q] * s.rl[q];
+    f = u * un;
+    us = chi * u;
+  } else if (q < S::N + S::D) {  // momentum
+    const int a = q - S::N;
+    u = s.rho * s.u[a];
+    f = u * un - s.sig[a];
+    us = chi * s.rho * (a == DIR ? Ss : s.u[a]);
+  } else if (q == S::cE) {
+    u = s.E;
+    double work = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) work += s.u[a] * s.sig[a];
+    f = s.E * un - work;
+    us = chi * (s.E + (Ss - un) * (s.rho * Ss + s.P / (Sk - un)));
+  } else if (q < S::cE + S::N) {  // phi_l
+    u = (double)W[S::wPHI(q - S::cE - 1)];
+    f = u * un;
+    us = chi * u;
+  } else if (S::S && q < S::cEP) {  // Vbar_ab
+    const int ab = q - S::cV(0, 0);
+    const int a = ab / 3, b = ab % 3;
+    u = (double)W[S::wV(0, 0) + ab];
+    f = u * un - (double)W[S::wV(DIR, b)] * s.u[a];
+    us = (a == DIR ? cn : ct) * u;
+  } else {  // phi_s rho_s eps_p
+    u = s.phi[sp] * s.rl[sp] * (double)W[S::wEP];
+    f = u * un;
+    us = chi * u;
+  }
+}
+
+// HLLC flux along DIR. Outputs the thermodynamic flux F[NT], the wall
+// velocity u* (the flux formula applied to the unit field, star value chi),
+// and the wall stretch row Vbar*_{DIR,:} (Godunov value at x/t = 0).
+// Davis wave speeds; HLLC-LM: central form with the acoustic terms scaled by
+// sin(min(1, Ma/Ma_lim) pi/2), Ma from the normal velocities.
+template <class S, int DIR, typename T>
+__device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& ustar, T* Vstar) {
+  SideState<S> L, R;
+  side_state<S, DIR>(P, WL, L);
+  side_state<S, DIR>(P, WR, R);
+  const double SL = fmin(L.un - L.c, R.un - R.c);
+  const double SR = fmax(L.un + L.c, R.un + R.c);
+  const double mL = L.rho * (SL - L.un), mR = R.rho * (SR - R.un);
+  const double Ss = (R.P - L.P + L.un * mL - R.un * mR) / (mL - mR);
+  const int sp = P.solid_phase < 0 ? 0 : P.solid_phase;
+  if (P.riemann == RS_HLLC_LM && SL < 0.0 && SR > 0.0) {
+    const double chiL = (SL - L.un) / (SL - Ss), chiR = (SR - R.un) / (SR - Ss);
+    double cnL = 1, ctL = 1, cnR = 1, ctR = 1;
+    if constexpr (S::S) {
+      ctL = cbrt(chiL); cnL = 1.0 / (ctL * ctL);
+      ctR = cbrt(chiR); cnR = 1.0 / (ctR * ctR);
+    }
+    const double Ma = fmax(fabs(L.un) / L.c, fabs(R.un) / R.c);
+    const double ph = sin(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
+    const double aS = fabs(Ss);
+#pragma unroll
+    for (int q = 0; q < S::NT; ++q) {
+      double uL, fL, usL, uR, fR, usR;
+      field_terms<S, DIR>(WL, L, q, sp, SL, Ss, chiL, cnL, ctL, uL, fL, usL);
+      field_terms<S, DIR>(WR, R, q, sp, SR, Ss, chiR, cnR, ctR, uR, fR, usR);
+      F[q] = (T)(0.5 * (fL + fR) + 0.5 * (ph * SL * (usL - uL) + aS * (usL - usR) + ph * SR * (usR - uR)));
+    }
+    ustar = (T)(0.5 * (L.un + R.un) + 0.5 * (ph * SL * (chiL - 1.0) + aS * (chiL - chiR) + ph * SR * (chiR - 1.0)));
+    if constexpr (S::S) {
+      const bool left = Ss >= 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double v = left ? (double)WL[S::wV(DIR, b)] * cnL : (double)WR[S::wV(DIR, b)] * cnR;
+        Vstar[b] = (T)v;
+      }
+    }
+    return;
+  }
+  // Toro HLLC: pick the side K whose fan region contains x/t = 0.
+  bool useL, star;
+  if (SL >= 0.0) { useL = true; star = false; }
+  else if (Ss >= 0.0) { useL = true; star = true; }
+  else if (SR > 0.0) { useL = false; star = true; }
+  else { useL = false; star = false; }
+  const SideState<S>& K = useL ? L : R;
+  const T* WK = useL ? WL : WR;
+  const double Sk = useL ? SL : SR;
+  const double chi = star ? (Sk - K.un) / (Sk - Ss) : 1.0;
+  double cn = 1.0, ct = 1.0;
+  if constexpr (S::S) {
+    if (star) { ct = cbrt(chi); cn = 1.0 / (ct * ct); }
+  }
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) {
+    double u, f, us;
+    field_terms<S, DIR>(WK, K, q, sp, Sk, Ss, chi, cn, ct, u, f, us);
+    F[q] = (T)(star ? f + Sk * (us - u) : f);
+  }
+  ustar = (T)(star ? K.un + Sk * (chi - 1.0) : K.un);
+  if constexpr (S::S) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Vstar[b] = (T)((double)WK[S::wV(DIR, b)] * (star ? cn : 1.0));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rigid-body velocity and seeding states (Sec. 2.3, Sec. 3.2)
+// ---------------------------------------------------------------------------
+
+__device__ inline void rigid_velocity(const Params& P, const double x[3], double v[3]) {
+  const double d0 = x[0] - P.ctr[0], d1 = x[1] - P.ctr[1], d2 = x[2] - P.ctr[2];
+  v[0] = P.vr[0] + P.om[1] * d2 - P.om[2] * d1;
+  v[1] = P.vr[1] + P.om[2] * d0 - P.om[0] * d2;
+  v[2] = P.vr[2] + P.om[0] * d1 - P.om[1] * d0;
+}
+
+// Mirror state of the seeding routine, as the Householder reflection
+// P = I - 2 n n^T (rotation-independent form of rotate, reflect the normal
+// velocity and the normal-tangential stretch components, rotate back):
+// u' = P u + 2 (v_r . n) n, Vbar' = P Vbar P, scalars unchanged.
+template <class S>
+__device__ inline void mirror(const double* Wi, const double n[3], const double v[3], double* Wm) {
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Wm[q] = Wi[q];
+  double un = 0.0, vn = 0.0;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) { un += Wi[S::wU(a)] * n[a]; vn += v[a] * n[a]; }
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) Wm[S::wU(a)] = Wi[S::wU(a)] - 2.0 * un * n[a] + 2.0 * vn * n[a];
+  if constexpr (S::S) {
+    // P V P = V - 2 n (n^T V) - 2 (V n) n^T + 4 (n^T V n) n n^T
+    double nV[3], Vn[3], nVn = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      nV[b] = n[0] * Wi[S::wV(0, b)] + n[1] * Wi[S::wV(1, b)] + n[2] * Wi[S::wV(2, b)];
+      Vn[b] = Wi[S::wV(b, 0)] * n[0] + Wi[S::wV(b, 1)] * n[1] + Wi[S::wV(b, 2)] * n[2];
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) nVn += nV[b] * n[b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        Wm[S::wV(a, b)] = Wi[S::wV(a, b)] - 2.0 * n[a] * nV[b] - 2.0 * Vn[a] * n[b] + 4.0 * nVn * n[a] * n[b];
+  }
+}
+
+// Riemann-problem seeding state: HLLC right star state of (mirror, interp)
+// along n, in primitive form (phasic densities * chi_R, normal velocity S*,
+// p* = p_R + rho_R (S_R - u_R)(S* - u_R), Vbar* = D Vbar_R with the
+// uniaxial stretch D along n; other fields from the interpolated state).
+template <class S>
+__device__ inline void riemann_seed(const Params& P, const double* Wm, const double* Wi, const double n[3],
+                                    double* Wo) {
+  double phL[kMaxMat], rL[kMaxMat], phR[kMaxMat], rR[kMaxMat];
+  phases_w<S>(Wm, phL, rL);
+  phases_w<S>(Wi, phR, rR);
+  double rhoL = 0.0, rhoR = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) { rhoL += phL[l] * rL[l]; rhoR += phR[l] * rR[l]; }
+  double uL = 0.0, uR = 0.0;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) { uL += Wm[S::wU(a)] * n[a]; uR += Wi[S::wU(a)] * n[a]; }
+  double J2L = 0.0, J2R = 0.0, HL[9], HR[9];
+  if constexpr (S::S) {
+    hencky3(Wm + S::wV(0, 0), HL, J2L);
+    hencky3(Wi + S::wV(0, 0), HR, J2R);
+  }
+  double c2L, GL, yL, c2R, GR, yR;
+  mix_c2_G<S>(P, phL, rL, J2L, Wm[S::wP], c2L, GL, yL);
+  mix_c2_G<S>(P, phR, rR, J2R, Wi[S::wP], c2R, GR, yR);
+  double PL = Wm[S::wP], PR = Wi[S::wP];
+  if constexpr (S::S) {
+    double nHnL = 0.0, nHnR = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) { nHnL += n[a] * HL[3 * a + b] * n[b]; nHnR += n[a] * HR[3 * a + b] * n[b]; }
+    PL -= 2.0 * GL * nHnL;
+    PR -= 2.0 * GR * nHnR;
+  }
+  const double cL = sqrt(c2L), cR = sqrt(c2R);
+  const double SL = fmin(uL - cL, uR - cR);
+  const double SR = fmax(uL + cL, uR + cR);
+  const double mL = rhoL * (SL - uL), mR = rhoR * (SR - uR);
+  const double Ss = (PR - PL + uL * mL - uR * mR) / (mL - mR);
+  const double chi = (SR - uR) / (SR - Ss);
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Wo[q] = Wi[q];
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) Wo[S::wRHO(l)] = Wi[S::wRHO(l)] * chi;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) Wo[S::wU(a)] = Wi[S::wU(a)] + (Ss - uR) * n[a];
+  Wo[S::wP] = Wi[S::wP] + rhoR * (SR - uR) * (Ss - uR);
+  if constexpr (S::S) {
+    const double ct = cbrt(chi), cn = 1.0 / (ct * ct);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double Dak = (a == k ? ct : 0.0) + (cn - ct) * n[a] * n[k];
+          s += Dak * Wi[S::wV(k, b)];
+        }
+        Wo[S::wV(a, b)] = s;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-stage sources of the elastoplastic system: unit-determinant
+// renormalisation of Vbar and perfect-plasticity radial return in Hencky
+// space (sigma_eq = sqrt(6) G |H| scaled back to the mixture yield stress
+// through Vbar <- exp((s-1) H) Vbar; eps_p grows by sqrt(2/3)(1-s)|H|;
+// rho E unchanged).
+// ---------------------------------------------------------------------------
+template <class S, typename T>
+__device__ inline void solid_sources(const Params& P, T* U) {
+  double V[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) V[q] = (double)U[S::cV(0, 0) + q];
+  const double det = V[0] * (V[4] * V[8] - V[5] * V[7]) - V[1] * (V[3] * V[8] - V[5] * V[6]) +
+                     V[2] * (V[3] * V[7] - V[4] * V[6]);
+  const double sc = 1.0 / cbrt(det);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) V[q] *= sc;
+  if (P.plastic) {
+    T Ut[S::NF], Wt[S::NF];
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Ut[q] = U[q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Ut[S::cV(0, 0) + q] = (T)V[q];
+    double H[9], J2;
+    cons_to_prim<S>(P, Ut, Wt, H, &J2);
+    double phi[kMaxMat], rl[kMaxMat];
+    phases_w<S>(Wt, phi, rl);
+    double c2, G, sY;
+    mix_c2_G<S>(P, phi, rl, J2, (double)Wt[S::wP], c2, G, sY);
+    const double Hn = sqrt(J2);
+    const double seq = 2.449489742783178 * G * Hn;
+    if (sY > 0.0 && seq > sY) {
+      const double s = sY / seq;
+      // exp((s-1) H) by the eigenvectors of H
+      double A[3][3], Q[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) A[a][b] = (s - 1.0) * H[3 * a + b];
+      jacobi3(A, Q);
+      double ev[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ev[k] = exp(A[k][k]);
+      double X[9], Vn[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[3 * a + b] = Q[a][0] * ev[0] * Q[b][0] + Q[a][1] * ev[1] * Q[b][1] + Q[a][2] * ev[2] * Q[b][2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Vn[3 * a + b] = X[3 * a] * V[b] + X[3 * a + 1] * V[3 + b] + X[3 * a + 2] * V[6 + b];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) V[q] = Vn[q];
+      const int sp = P.solid_phase;
+      const double as = phi[sp] * rl[sp];
+      U[S::cEP] = (T)((double)U[S::cEP] + as * 0.816496580927726 * (1.0 - s) * Hn);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) U[S::cV(0, 0) + q] = (T)V[q];
+}
+
+}  // namespace rbdi

@@ -1,0 +1,273 @@
+"""Thin ctypes binding of librbdi (include/rbdi.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library. The names follow the C entry points. Loading fails loudly if
+the library has not been built (``paper_2111_11806_amd.build.build()``);
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+EOS = {"ideal": 0, "stiffened": 1, "romenskii": 2}
+BC = {"transmissive": 0, "reflective": 1, "dirichlet": 2, "periodic": 3}
+RECON = {"muscl": 0, "bvd_thinc": 1}
+RIEMANN = {"hllc": 0, "hllc_lm": 1}
+SEED = {"original": 0, "riemann": 1, "none": 2}
+PROBE = {"stepout": 0, "fixed": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+RBDI_OK = 0
+RBDI_ERR_NONPHYSICAL = -4
+
+
+class RbdiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rbdi error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
+                ("origin", ctypes.c_double * 3), ("nmat", ctypes.c_int), ("solid", ctypes.c_int),
+                ("bc", ctypes.c_int * 6), ("recon", ctypes.c_int), ("riemann", ctypes.c_int),
+                ("seed", ctypes.c_int), ("probe", ctypes.c_int), ("plastic", ctypes.c_int),
+                ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class Eos(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("gamma", ctypes.c_double), ("pinf", ctypes.c_double),
+                ("rho0", ctypes.c_double), ("K0", ctypes.c_double), ("G0", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("Gamma0", ctypes.c_double),
+                ("sigma_y", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_longlong), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
+                ("band_cells", ctypes.c_longlong), ("seeded", ctypes.c_longlong),
+                ("probe_fail", ctypes.c_longlong), ("nonphysical", ctypes.c_int), ("first_bad", ctypes.c_longlong)]
+
+
+_lib = None
+
+EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rbdi_set_material",
+           "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
+           "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
+           "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
+           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times"]
+NUM_KCLASS = 6
+KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt"]
+
+
+def lib_path():
+    return _build.LIB
+
+
+def load():
+    """Load librbdi.so (built in-tree). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"librbdi is not built ({path}); run paper_2111_11806_amd.build.build()")
+    L = ctypes.CDLL(path)
+    vp, ip, dp, cp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_char_p
+    L.rbdi_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    L.rbdi_destroy.argtypes = [vp]
+    L.rbdi_nfields.argtypes = [vp]
+    L.rbdi_set_stream.argtypes = [vp, vp]
+    L.rbdi_set_material.argtypes = [vp, ip, ctypes.POINTER(Eos)]
+    L.rbdi_set_bc_state.argtypes = [vp, ip, dp]
+    for nm in ("rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons", "rbdi_set_state_cons"):
+        getattr(L, nm).argtypes = [vp, vp, ip]
+    L.rbdi_set_rigid_sdf.argtypes = [vp, vp, ip, ctypes.c_double, dp, dp, dp]
+    L.rbdi_set_rigid_motion.argtypes = [vp, dp, dp, dp]
+    L.rbdi_compute_dt.argtypes = [vp, ctypes.c_double, dp]
+    L.rbdi_step.argtypes = [vp, ctypes.c_double]
+    L.rbdi_advance.argtypes = [vp, ctypes.c_double, ip, ctypes.c_double]
+    L.rbdi_status.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.rbdi_rigid_force.argtypes = [vp, dp, dp, dp]
+    L.rbdi_conserved_totals.argtypes = [vp, dp]
+    L.rbdi_last_error.restype = cp
+    L.rbdi_set_kernel_timing.argtypes = [vp, ip]
+    L.rbdi_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != RBDI_OK:
+        raise RbdiError(rc, load().rbdi_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _arr(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def make_eos(m) -> Eos:
+    e = Eos()
+    e.kind = EOS[m["kind"]]
+    if m["kind"] in ("ideal", "stiffened"):
+        e.gamma = m["gamma"]
+        e.pinf = m.get("pinf", 0.0)
+    else:
+        e.rho0, e.K0, e.G0 = m["rho0"], m["K0"], m["G0"]
+        e.alpha, e.beta, e.Gamma0 = m["alpha"], m["beta"], m["Gamma0"]
+        e.sigma_y = m.get("sigY", 0.0)
+    return e
+
+
+def make_desc(prob, precision="fp64") -> Desc:
+    d = Desc()
+    d.dim = prob.dim
+    for a in range(3):
+        d.n[a] = prob.n[a]
+        d.dx[a] = prob.dx[a]
+        d.origin[a] = prob.origin[a]
+    d.nmat = len(prob.materials)
+    d.solid = int(prob.solid)
+    for q in range(6):
+        d.bc[q] = BC[prob.bc[q]]
+    d.recon = RECON[prob.recon]
+    d.riemann = RIEMANN[prob.riemann]
+    d.seed = SEED[prob.seed]
+    d.probe = PROBE[prob.probe]
+    d.plastic = int(prob.plastic)
+    d.thinc_beta = prob.thinc_beta
+    d.lm_mach = prob.lm_mach
+    d.precision = PRECISION[precision]
+    return d
+
+
+class Solver:
+    """One librbdi instance of a :class:`paper_2111_11806_amd.inputs.Problem`."""
+
+    def __init__(self, prob, precision="fp64", stream=None):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.rbdi_create(ctypes.byref(make_desc(prob, precision)), ctypes.byref(h)))
+        self._h = h
+        self.prob = prob
+        self.precision = precision
+        self.nf = L.rbdi_nfields(h)
+        if stream is not None:
+            self.set_stream(stream)
+        for l, m in enumerate(prob.materials):
+            _check(L.rbdi_set_material(h, l, ctypes.byref(make_eos(m))))
+        for face, W in prob.bc_states.items():
+            _check(L.rbdi_set_bc_state(h, face, _dp(_arr(W, self.nf))))
+        self.set_state_prim(prob.W0)
+        if prob.sdf is not None:
+            self.set_rigid_sdf(prob.sdf, prob.width, prob.v_r, prob.omega, prob.center)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load().rbdi_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.prob.n
+        return (self.nf, nz, ny, nx)
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(load().rbdi_set_stream(self._h, ctypes.c_void_p(raw or 0)))
+
+    def set_state_prim(self, W):
+        if hasattr(W, "data_ptr"):
+            _check(load().rbdi_set_state_prim(self._h, ctypes.c_void_p(W.data_ptr()), 1))
+        else:
+            a = _arr(W, int(np.prod(self.shape)))
+            _check(load().rbdi_set_state_prim(self._h, a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_state_cons(self, U):
+        a = _arr(U, int(np.prod(self.shape)))
+        _check(load().rbdi_set_state_cons(self._h, a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def get_state_prim(self):
+        out = np.empty(self.shape)
+        _check(load().rbdi_get_state_prim(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def get_state_cons(self):
+        out = np.empty(self.shape)
+        _check(load().rbdi_get_state_cons(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def set_rigid_sdf(self, sdf, width, v, omega, center):
+        a = _arr(sdf, int(np.prod(self.shape[1:])))
+        _check(load().rbdi_set_rigid_sdf(self._h, a.ctypes.data_as(ctypes.c_void_p), 0, float(width),
+                                         _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3))))
+
+    def set_rigid_motion(self, v, omega, center):
+        _check(load().rbdi_set_rigid_motion(self._h, _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3))))
+
+    def compute_dt(self, cfl):
+        out = ctypes.c_double()
+        _check(load().rbdi_compute_dt(self._h, float(cfl), ctypes.byref(out)))
+        return out.value
+
+    def step(self, dt):
+        _check(load().rbdi_step(self._h, float(dt)))
+
+    def advance(self, cfl, nsteps, t_end=0.0):
+        _check(load().rbdi_advance(self._h, float(cfl), int(nsteps), float(t_end)))
+
+    def status(self, raise_on_error=True):
+        st = Stats()
+        rc = load().rbdi_status(self._h, ctypes.byref(st))
+        if rc != RBDI_OK and (raise_on_error or rc != RBDI_ERR_NONPHYSICAL):
+            _check(rc)
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    @property
+    def t(self):
+        return self.status(raise_on_error=False)["t"]
+
+    def rigid_force(self, center):
+        F = np.zeros(3)
+        T = np.zeros(3)
+        _check(load().rbdi_rigid_force(self._h, _dp(_arr(center, 3)), _dp(F), _dp(T)))
+        return F, T
+
+    def conserved_totals(self):
+        out = np.zeros(2 * self.nf)
+        _check(load().rbdi_conserved_totals(self._h, _dp(out)))
+        return out[: self.nf], out[self.nf:]
+
+    def set_kernel_timing(self, enable):
+        _check(load().rbdi_set_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """{class: (total ms, launches)} of the launches recorded since the last call."""
+        ms = np.zeros(NUM_KCLASS)
+        n = (ctypes.c_longlong * NUM_KCLASS)()
+        _check(load().rbdi_kernel_times(self._h, _dp(ms), n))
+        return {KCLASS[c]: (float(ms[c]), int(n[c])) for c in range(NUM_KCLASS)}
+
+    def run(self, dts):
+        for dt in dts:
+            self.step(dt)

@@ -1,0 +1,45 @@
+"""The C-ABI library loads and exports every symbol include/rbdi.h declares
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "rbdi.h")).read()
+    return sorted(set(re.findall(r"RBDI_API\s+[\w\s\*]+?\b(rbdi_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_api():
+    syms = declared_symbols()
+    for s in ("rbdi_create", "rbdi_step", "rbdi_set_rigid_sdf", "rbdi_rigid_force", "rbdi_set_material"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2111_11806_amd import build, rbdi
+    if not os.path.exists(build.LIB):
+        build.build(force=False)
+    lib = rbdi.load()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+    out = subprocess.run(["nm", "-D", "--defined-only", build.LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (rbdi_\w+)", out))
+    assert set(declared_symbols()) <= exported
+    assert set(rbdi.EXPORTS) == set(declared_symbols())
+
+
+def test_bad_arguments_fail_without_gpu_work():
+    from paper_2111_11806_amd import rbdi
+    lib = rbdi.load()
+    h = ctypes.c_void_p()
+    d = rbdi.Desc()
+    d.dim = 4
+    assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"dim" in lib.rbdi_last_error()
+    assert lib.rbdi_create(None, ctypes.byref(h)) == -1

@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Both sides start from the same seeded inputs and take the same dt sequence
+(the oracle's CFL steps). Bars: relative L1 per conserved field <= 1e-10 for
+FP64, <= 1e-4 for FP32; FP64 reductions (force, torque, totals, dt) to 1e-12
+relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_11806_amd import inputs
+from parity_util import announce, rel_l1, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rbdi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2111_11806_amd import rbdi as r
+    r.load()
+    return r
+
+
+def _pair(rbdi, prob, nsteps, precision="fp64", t_end=None):
+    announce(f"{prob.name} n={prob.n} steps={nsteps} {precision} recon={prob.recon} seed={prob.seed}")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(nsteps=nsteps, t_end=t_end)
+    gpu = rbdi.Solver(prob, precision)
+    gpu.run(dts)
+    st = gpu.status()
+    assert st["nonphysical"] == 0
+    return orc, gpu, dts
+
+
+def _check(orc, gpu, tol, fields=None):
+    a, b = gpu.get_state_cons(), orc.get_state_cons()
+    rl = rel_l1(a, b)
+    if fields is not None:
+        rl = rl[fields]
+    assert np.all(rl <= tol), rl
+    return rl
+
+
+# ---------------------------------------------------------------------------
+# 1D
+# ---------------------------------------------------------------------------
+
+def test_sod_wall_full_run_fp64(rbdi):
+    """Sod tube with a static rigid wall (400 cells, MUSCL + HLLC, CFL 0.8) to
+    t = 0.3: conserved fields, primitives and the wall force match."""
+    prob = inputs.sod_wall(400)
+    orc, gpu, dts = _pair(rbdi, prob, nsteps=10**6)
+    assert abs(sum(dts) - 0.3) < 1e-12
+    _check(orc, gpu, TOL64)
+    assert np.all(rel_l1(gpu.get_state_prim(), orc.get_state_prim()) <= TOL64)
+    Fg, _ = gpu.rigid_force([0, 0, 0])
+    Fo, _ = orc.rigid_force([0, 0, 0])
+    assert Fg[0] == pytest.approx(Fo[0], rel=1e-10)
+    st = gpu.status()
+    assert st["steps"] == len(dts) and st["seeded"] > 0
+
+
+@pytest.mark.parametrize("recon", ["muscl", "bvd_thinc"])
+@pytest.mark.parametrize("seed", ["original", "riemann"])
+def test_piston_moving_body(rbdi, recon, seed):
+    prob = inputs.piston_1d(300, recon=recon)
+    prob.seed = seed
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=120)
+    _check(orc, gpu, TOL64)
+
+
+@pytest.mark.parametrize("n", [3, 5, 57, 58, 59, 117, 401])
+def test_ragged_1d_sizes(rbdi, n):
+    """Sizes below, at and around the 58-cell wavefront tile, periodic and
+    reflective ends."""
+    prob = inputs.riemann_1d([1.0, 0.3, 1.0], [0.125, -0.2, 0.1], [inputs.ideal(1.4)], n=n, t_end=0.05,
+                             recon="bvd_thinc")
+    prob.bc = ["reflective"] * 6
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=15)
+    _check(orc, gpu, TOL64)
+
+
+def test_two_phase_1d_water_air(rbdi):
+    eps = 1e-6
+    mats = [inputs.stiffened(1.4, 0.0), inputs.stiffened(4.4, 6e8)]
+    prob = inputs.riemann_1d([eps, 50.0, 1000.0, 0.0, 1e9], [1 - eps, 50.0, 1000.0, 0.0, 1e5], mats, n=300,
+                             t_end=1e-4, recon="bvd_thinc")
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=60)
+    _check(orc, gpu, TOL64)
+
+
+# ---------------------------------------------------------------------------
+# 2D
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("riemann", ["hllc", "hllc_lm"])
+def test_shock_cylinder_reduced_grid(rbdi, riemann):
+    """Mach 2.8 shock over the cylinder on 160 x 80 (several tiles and ragged
+    tails in x and y), 80 steps."""
+    prob = inputs.shock_cylinder(160, 80, riemann=riemann)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=80)
+    _check(orc, gpu, TOL64)
+    Fg, Tg = gpu.rigid_force([0.3, 0.25, 0.0])
+    Fo, To = orc.rigid_force([0.3, 0.25, 0.0])
+    assert np.allclose(Fg, Fo, rtol=1e-10, atol=1e-12 * np.abs(Fo).max())
+    assert np.allclose(Tg, To, rtol=1e-9, atol=1e-12 * max(np.abs(Fo).max(), 1e-300))
+    ta, tf = gpu.conserved_totals()
+    oa, of = orc.conserved_totals()
+    assert np.allclose(ta, oa, rtol=1e-10, atol=1e-14)
+    assert np.allclose(tf, of, rtol=1e-10, atol=1e-14)
+
+
+def test_shock_cylinder_riemann_seeding_and_fixed_probe(rbdi):
+    prob = inputs.shock_cylinder(128, 64)
+    prob.seed = "riemann"
+    prob.probe = "fixed"
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=50)
+    _check(orc, gpu, TOL64)
+
+
+def test_shock_cylinder_fp32(rbdi):
+    prob = inputs.shock_cylinder(160, 80)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=80, precision="fp32")
+    rl = _check(orc, gpu, TOL32)
+    print("fp32 rel L1 per field", rl)
+
+
+def test_cfl_dt_matches(rbdi):
+    prob = inputs.shock_cylinder(200, 100)
+    orc = oracle.Oracle(prob)
+    gpu = rbdi.Solver(prob, "fp64")
+    for _ in range(3):
+        dto = orc.compute_dt(0.4)
+        dtg = gpu.compute_dt(0.4)
+        assert dtg == pytest.approx(dto, rel=1e-13)
+        orc.step(dto)
+        gpu.step(dto)
+
+
+def test_advance_device_dt_equals_host_loop(rbdi):
+    """rbdi_advance (dt on the device, no host sync) equals compute_dt + step."""
+    prob = inputs.shock_cylinder(128, 64)
+    a = rbdi.Solver(prob, "fp64")
+    b = rbdi.Solver(prob, "fp64")
+    a.advance(0.4, 20, 0.0)
+    for _ in range(20):
+        b.step(b.compute_dt(0.4))
+    assert np.array_equal(a.get_state_cons(), b.get_state_cons())
+    assert a.status()["t"] == b.status()["t"]
+
+
+def test_advance_clips_at_t_end(rbdi):
+    prob = inputs.sod_wall(400)
+    a = rbdi.Solver(prob, "fp64")
+    a.advance(0.8, 2000, 0.3)
+    st = a.status()
+    assert st["t"] == pytest.approx(0.3, abs=1e-14)
+    orc = oracle.Oracle(prob)
+    dts = orc.run()
+    assert st["steps"] == len(dts)
+    assert np.all(rel_l1(a.get_state_cons(), orc.get_state_cons()) <= TOL64)
+
+
+def test_air_water_moving_ellipse(rbdi):
+    """Two stiffened gases, THINC on r and phi, moving rigid ellipse (reduced
+    grid 192 x 96, 40 steps)."""
+    prob = inputs.air_water(192, 96)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=40)
+    _check(orc, gpu, TOL64)
+
+
+def test_quiescent_body_bitwise_steady(rbdi):
+    prob = inputs.quiescent_body(64, 40)
+    gpu = rbdi.Solver(prob, "fp64")
+    U0 = gpu.get_state_cons()
+    for _ in range(20):
+        gpu.step(0.004)
+    assert np.array_equal(U0, gpu.get_state_cons())
+
+
+def test_conservation_periodic_2d_two_phase(rbdi):
+    prob = inputs.periodic_box(dim=2, n=48, nmat=2)
+    gpu = rbdi.Solver(prob, "fp64")
+    t0, _ = gpu.conserved_totals()
+    for _ in range(200):
+        gpu.step(0.2 * gpu.compute_dt(1.0))
+    t1, _ = gpu.conserved_totals()
+    nc = 2 + 2 + 1
+    scale = np.abs(gpu.get_state_cons()[:nc]).sum(axis=(1, 2, 3)) / 48 ** 2
+    assert np.all(np.abs(t1[:nc] - t0[:nc]) <= 1e-12 * scale)
+
+
+# ---------------------------------------------------------------------------
+# 3D
+# ---------------------------------------------------------------------------
+
+def test_periodic_3d_single_gas(rbdi):
+    prob = inputs.periodic_box(dim=3, n=20, nmat=1)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=10)
+    _check(orc, gpu, TOL64)
+
+
+def test_3d_sphere_in_shock(rbdi):
+    """A planar pressure pulse over a static rigid sphere on 24^3."""
+    n = 24
+    prob = inputs.periodic_box(dim=3, n=n, nmat=1)
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    W = np.zeros((6, n, n, n))
+    W[0] = np.where(X < 0.2, 2.0, 1.0)
+    W[1] = np.where(X < 0.2, 0.8, 0.0)
+    W[4] = np.where(X < 0.2, 2.5, 1.0)
+    prob.W0 = W
+    prob.bc = ["transmissive"] * 6
+    prob.sdf = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) - 0.2
+    prob.seed = "original"
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=12)
+    _check(orc, gpu, TOL64)
