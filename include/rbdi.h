@@ -110,9 +110,9 @@ typedef struct {
   long long steps;        /* completed steps */
   double t;               /* simulated time */
   double last_dt;         /* dt of the last step */
-  long long band_cells;   /* rigid cells with a nonzero normal (last seeding) */
-  long long seeded;       /* cells seeded (cumulative) */
-  long long probe_fail;   /* rigid band cells without a valid probe (cumulative) */
+  long long band_cells;   /* rigid cells with a nonzero normal (last band build) */
+  long long seeded;       /* cells seeded (cumulative over steps) */
+  long long probe_fail;   /* of band_cells, those without a valid probe (last band build) */
   int nonphysical;        /* 1 once a non-admissible updated cell was found */
   long long first_bad;    /* linear interior index of the first such cell, or -1 */
 } rbdi_stats;
@@ -183,7 +183,8 @@ RBDI_API int rbdi_step(rbdi_handle* h, double dt);
 RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end);
 
 /* Synchronise and read the counters; returns NONPHYSICAL if a non-admissible
- * cell was flagged (st is filled either way). */
+ * cell was flagged, OOM if the rigid band outgrew the seeding task buffer
+ * (one quarter of the cells); st is filled either way. */
 RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st);
 
 /* Force and torque about center exerted by the material on the rigid body,

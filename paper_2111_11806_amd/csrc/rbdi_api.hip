@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,7 +43,13 @@ struct rbdi_handle {
   void* U[3] = {nullptr, nullptr, nullptr};
   void* D = nullptr;
   double* stage_buf = nullptr;  // FP64 staging for API transfers (nf * ncell)
-  int* band = nullptr;
+  SeedTask* tasks = nullptr;    // seeding tasks of the rigid band
+  int task_cap = 0;
+  int par = 0;                  // parity of the next step
+  bool cfl_valid = false;       // CFL partials of the current state are in cflpart
+  double* cflpart = nullptr;    // CFL partials (one per block of their producer)
+  int npart = 0;                // number of valid partials
+  int part_cap = 0;
   DevScalars* sc = nullptr;
   double* part = nullptr;       // reduction partials
   double* red_out = nullptr;    // reduction results (device)
@@ -95,12 +102,13 @@ struct Ops {
   void (*state_to_f64)(rbdi_handle*, double*);
   void (*f64_to_state)(rbdi_handle*, const double*);
   void (*r_from_sdf)(rbdi_handle*, const double*, double);
-  void (*band)(rbdi_handle*);
-  void (*seed)(rbdi_handle*);
-  void (*stages)(rbdi_handle*);
-  void (*dt_partial)(rbdi_handle*);
+  void (*band)(rbdi_handle*, const StepArgs&);
+  void (*seed)(rbdi_handle*, const StepArgs&);
+  void (*stages)(rbdi_handle*, const StepArgs&);
+  void (*cfl)(rbdi_handle*);
   void (*force)(rbdi_handle*, const double*);
   void (*totals)(rbdi_handle*);
+  int (*part_blocks)(const Params&);
 };
 
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -129,55 +137,70 @@ struct Impl {
     hipLaunchKernelGGL((k_r_from_sdf<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
                        sdf, inv_w, u(h, 0));
   }
-  static void band(rbdi_handle* h) {
+  static void band(rbdi_handle* h, const StepArgs& A) {
     Timed tm(h, 4);
-    hipLaunchKernelGGL(k_reset_band, dim3(1), dim3(1), 0, h->stream, h->sc);
+    hipLaunchKernelGGL(k_band_reset, dim3(1), dim3(1), 0, h->stream, h->sc, A);
     hipLaunchKernelGGL((k_band<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
-                       (const T*)u(h, 0), h->band, h->sc);
-    hipLaunchKernelGGL(k_band_stat, dim3(1), dim3(1), 0, h->stream, h->sc);
+                       (const T*)u(h, 0), h->tasks, h->task_cap, h->sc, A);
   }
-  static void seed(rbdi_handle* h) {
+  static void seed(rbdi_handle* h, const StepArgs& A) {
     Timed tm(h, 3);
-    hipLaunchKernelGGL((k_seed<S, T>), dim3(512), dim3(256), 0, h->stream, h->P, u(h, 0), (const int*)h->band,
-                       h->sc);
+    hipLaunchKernelGGL((k_seed<S, T>), dim3(256), dim3(256), 0, h->stream, h->P, u(h, 0),
+                       (const SeedTask*)h->tasks, h->task_cap, h->sc, A);
   }
-  template <int DIR, int MODE>
-  static void sweep(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, double b, int stage) {
+  static int x_wpb() { return S::D == 1 ? 1 : kWPB; }
+  static dim3 x_grid(const Params& P) {
+    const unsigned nseg = (unsigned)((P.n[0] + kOut - 1) / kOut);
+    return dim3(nseg, (unsigned)((P.n[1] + x_wpb() - 1) / x_wpb()), (unsigned)P.n[2]);
+  }
+  static int x_partials(const Params& P) {
+    const dim3 g = x_grid(P);
+    return (int)(g.x * g.y * g.z) * x_wpb();
+  }
+  static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
+    Timed tm(h, 0);
+    hipLaunchKernelGGL((k_sweep_x<S, T>), x_grid(h->P), dim3(kWave * x_wpb()), 0, h->stream, h->P, Uin, U0,
+                       (const T*)h->D, Uout, h->sc, h->cflpart, A, b, stage);
+  }
+  template <int DIR, int MODE, bool REDUCE>
+  static void sweep_t(rbdi_handle* h, const T* Uin, const StepArgs& A) {
     const Params& P = h->P;
-    const int nd = P.n[DIR];
-    const unsigned nseg = (unsigned)((nd + kOut - 1) / kOut);
-    const int wpb = S::D == 1 ? 1 : kWPB;
-    dim3 grid;
-    if (DIR == 0) grid = dim3(nseg, (unsigned)((P.n[1] + wpb - 1) / wpb), (unsigned)P.n[2]);
-    else if (DIR == 1) grid = dim3((unsigned)((P.n[0] + wpb - 1) / wpb), nseg, (unsigned)P.n[2]);
-    else grid = dim3((unsigned)((P.n[0] + wpb - 1) / wpb), (unsigned)P.n[1], nseg);
+    constexpr int TC = tile_cols<S, T>();
+    const unsigned nseg = (unsigned)((P.n[DIR] + kOut - 1) / kOut);
+    const unsigned gx = (unsigned)((P.n[0] + TC - 1) / TC);
+    const dim3 grid = DIR == 1 ? dim3(gx, nseg, (unsigned)P.n[2]) : dim3(gx, (unsigned)P.n[1], nseg);
     Timed tm(h, DIR);
-    hipLaunchKernelGGL((k_sweep<S, T, DIR, MODE>), grid, dim3(kWave * wpb), 0, h->stream, P, Uin, U0,
-                       static_cast<T*>(h->D), Uout, h->sc, b, stage);
+    hipLaunchKernelGGL((k_sweep_tile<S, T, DIR, MODE, REDUCE>), grid, dim3(256), 0, h->stream, P, Uin,
+                       static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
   }
-  static void stages(rbdi_handle* h) {
+  static void stages(rbdi_handle* h, const StepArgs& A) {
     const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
     const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
+    if constexpr (S::D == 1) {
+      Timed tm(h, 5);
+      hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(256), 0, h->stream, h->sc, (const double*)h->cflpart, A);
+    }
     for (int s = 0; s < 3; ++s) {
       const T* Uin = u(h, in_[s]);
       const T* U0 = u(h, 0);
       T* Uout = u(h, out_[s]);
       if constexpr (S::D == 3) {
-        sweep<2, 0>(h, Uin, U0, Uout, bc[s], s);
-        sweep<1, 1>(h, Uin, U0, Uout, bc[s], s);
-        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
+        if (s == 0) sweep_t<2, 0, true>(h, Uin, A);
+        else sweep_t<2, 0, false>(h, Uin, A);
+        sweep_t<1, 1, false>(h, Uin, A);
       } else if constexpr (S::D == 2) {
-        sweep<1, 0>(h, Uin, U0, Uout, bc[s], s);
-        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
-      } else {
-        sweep<0, 2>(h, Uin, U0, Uout, bc[s], s);
+        if (s == 0) sweep_t<1, 0, true>(h, Uin, A);
+        else sweep_t<1, 0, false>(h, Uin, A);
       }
+      sweep_x(h, Uin, U0, Uout, A, bc[s], s);
     }
+    h->npart = x_partials(h->P);
   }
-  static void dt_partial(rbdi_handle* h) {
+  static void cfl(rbdi_handle* h) {
     Timed tm(h, 5);
-    hipLaunchKernelGGL((k_dt_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
-                       (const T*)u(h, 0), (const DevScalars*)h->sc, h->part);
+    hipLaunchKernelGGL((k_cfl<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P, (const T*)u(h, 0),
+                       (const DevScalars*)h->sc, h->par, h->cflpart);
+    h->npart = kRedBlocks;
   }
   static void force(rbdi_handle* h, const double* c) {
     hipLaunchKernelGGL((k_force_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
@@ -191,9 +214,10 @@ struct Impl {
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, h->stream, (const double*)h->part, kRedBlocks,
                        2 * S::NF, h->red_out);
   }
+  static int part_blocks(const Params& P) { return std::max(x_partials(P), kRedBlocks); }
   static const Ops* ops() {
     static const Ops o = {prim_to_state, state_to_prim, state_to_f64, f64_to_state, r_from_sdf, band, seed,
-                          stages, dt_partial, force, totals};
+                          stages, cfl, force, totals, part_blocks};
     return &o;
   }
 };
@@ -226,10 +250,11 @@ void free_all(rbdi_handle* h) {
   h->ev.clear();
   for (auto& p : h->U)
     if (p) { (void)hipFree(p); p = nullptr; }
-  void* ptrs[] = {h->D, h->stage_buf, h->band, h->sc, h->part, h->red_out};
+  void* ptrs[] = {h->D, h->stage_buf, h->tasks, h->sc, h->part, h->red_out, h->cflpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  h->D = nullptr; h->stage_buf = nullptr; h->band = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
+  h->D = nullptr; h->stage_buf = nullptr; h->tasks = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
+  h->cflpart = nullptr;
 }
 
 }  // namespace
@@ -307,10 +332,13 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMalloc(&h->U[k], state_bytes);
   if (e == hipSuccess) e = hipMalloc(&h->D, state_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&h->stage_buf, (size_t)ncell * h->nf * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&h->band, (size_t)ncell * sizeof(int));
+  h->task_cap = (int)std::max<long long>(4096, ncell / 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->tasks, (size_t)h->task_cap * sizeof(SeedTask));
   if (e == hipSuccess) e = hipMalloc((void**)&h->sc, sizeof(DevScalars));
   if (e == hipSuccess) e = hipMalloc((void**)&h->part, sizeof(double) * kRedBlocks * 2 * kMaxF);
   if (e == hipSuccess) e = hipMalloc((void**)&h->red_out, sizeof(double) * 2 * kMaxF);
+  h->part_cap = ops->part_blocks(P);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->cflpart, sizeof(double) * h->part_cap);
   if (e != hipSuccess) {
     free_all(h);
     delete h;
@@ -318,6 +346,7 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   }
   DevScalars zero{};
   zero.first_bad = -1;
+  P.r_static = 1;
   e = hipMemcpy(h->sc, &zero, sizeof(zero), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->U[0], 0, state_bytes);
   if (e != hipSuccess) {
@@ -359,6 +388,7 @@ RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* e) {
     m.Gam = e->gamma - 1.0;
     m.invGam = 1.0 / m.Gam;
     m.Bfl = e->gamma * pinf / m.Gam;
+    m.gGam = e->gamma / m.Gam;
   } else if (e->kind == RBDI_EOS_ROMENSKII) {
     if (!h->desc.solid) return fail(RBDI_ERR_BAD_ARG, "Romenskii material needs desc.solid = 1");
     if (!(e->rho0 > 0.0) || !(e->K0 >= 0.0) || !(e->G0 >= 0.0) || !(e->alpha > 0.0) || !(e->Gamma0 > 0.0) ||
@@ -416,6 +446,7 @@ RBDI_API int rbdi_set_state_prim(rbdi_handle* h, const double* W, int on_device)
   h->ops->prim_to_state(h, h->stage_buf);
   h->have_state = true;
   h->band_valid = false;
+  h->cfl_valid = false;
   HIP_OK(hipStreamSynchronize(h->stream));
   return check_launch();
 }
@@ -429,6 +460,7 @@ RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device)
   h->ops->f64_to_state(h, h->stage_buf);
   h->have_state = true;
   h->band_valid = false;
+  h->cfl_valid = false;
   HIP_OK(hipStreamSynchronize(h->stream));
   return check_launch();
 }
@@ -467,11 +499,12 @@ RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device
   int rc = rbdi_set_rigid_motion(h, v, omega, center);
   if (rc) return rc;
   h->band_valid = false;
+  h->cfl_valid = false;
   HIP_OK(hipStreamSynchronize(h->stream));
   return check_launch();
 }
 
-__global__ void k_set_motion_time(DevScalars* sc) { sc->t_motion = sc->t; }
+__global__ void k_set_motion_time(DevScalars* sc, int par) { sc->t_motion = sc->t[par]; }
 
 RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3], const double center[3]) {
   if (!h || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
@@ -485,28 +518,40 @@ RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const doub
     moving = moving || v[a] != 0.0 || omega[a] != 0.0;
   }
   h->dynamic_r = moving;
-  hipLaunchKernelGGL(k_set_motion_time, dim3(1), dim3(1), 0, h->stream, h->sc);
+  h->P.r_static = moving ? 0 : 1;
+  h->cfl_valid = false;
+  hipLaunchKernelGGL(k_set_motion_time, dim3(1), dim3(1), 0, h->stream, h->sc, h->par);
   return check_launch();
 }
 
-static void enqueue_step(rbdi_handle* h) {
+// One step: (CFL minimum if stale) -> band (once for a static body) ->
+// seeding -> three stages of sweeps. The first kernel of the step does the
+// step bookkeeping on the device.
+static void enqueue_step(rbdi_handle* h, double dt_fixed, double cfl, double t_end) {
+  if (dt_fixed <= 0.0 && !h->cfl_valid) h->ops->cfl(h);
+  StepArgs A;
+  A.par = h->par;
+  A.npart = h->npart;
+  A.cfl = cfl;
+  A.t_end = t_end;
+  A.dt_fixed = dt_fixed;
   if (h->P.seed != RBDI_SEED_NONE) {
     if (!h->band_valid || h->dynamic_r) {
-      h->ops->band(h);
+      h->ops->band(h, A);
       h->band_valid = true;
     }
-    h->ops->seed(h);
+    h->ops->seed(h, A);
   }
-  h->ops->stages(h);
-  hipLaunchKernelGGL(k_end_step, dim3(1), dim3(1), 0, h->stream, h->sc);
+  h->ops->stages(h, A);
+  h->par ^= 1;
+  h->cfl_valid = true;
 }
 
 RBDI_API int rbdi_step(rbdi_handle* h, double dt) {
   if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBDI_ERR_BAD_ARG, "dt must be positive and finite");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
-  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, h->stream, h->sc, dt);
-  enqueue_step(h);
+  enqueue_step(h, dt, 0.0, 0.0);
   return check_launch();
 }
 
@@ -514,14 +559,19 @@ RBDI_API int rbdi_compute_dt(rbdi_handle* h, double cfl, double* dt) {
   if (!h || !dt) return fail(RBDI_ERR_BAD_ARG, "null argument");
   if (!(cfl > 0.0)) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
-  h->ops->dt_partial(h);
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, kRedBlocks, cfl, 0.0,
-                     h->sc, h->red_out);
-  HIP_OK(hipMemcpyAsync(dt, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (!h->cfl_valid) {
+    h->ops->cfl(h);
+    h->cfl_valid = true;
+  }
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, h->stream, (const double*)h->cflpart, h->npart,
+                     h->red_out);
+  double m = 0.0;
+  HIP_OK(hipMemcpyAsync(&m, h->red_out, sizeof(m), hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   int rc = check_launch();
   if (rc) return rc;
-  if (!std::isfinite(*dt) || !(*dt > 0.0) || *dt > 1e299) return fail(RBDI_ERR_NONPHYSICAL, "no finite CFL time step");
+  *dt = m > 0.0 ? cfl / m : 0.0;
+  if (!std::isfinite(*dt) || !(*dt > 0.0)) return fail(RBDI_ERR_NONPHYSICAL, "no finite CFL time step");
   return RBDI_OK;
 }
 
@@ -529,12 +579,7 @@ RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end) 
   if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
   if (!(cfl > 0.0) || nsteps < 0) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 and nsteps >= 0");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
-  for (int s = 0; s < nsteps; ++s) {
-    h->ops->dt_partial(h);
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, kRedBlocks, cfl, t_end,
-                       h->sc, (double*)nullptr);
-    enqueue_step(h);
-  }
+  for (int s = 0; s < nsteps; ++s) enqueue_step(h, 0.0, cfl, t_end);
   return check_launch();
 }
 
@@ -564,16 +609,17 @@ RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st) {
   HIP_OK(hipMemcpyAsync(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   st->steps = s.steps;
-  st->t = s.t;
+  st->t = s.t[h->par];
   st->last_dt = s.last_dt;
-  st->band_cells = s.band_cells;
+  st->band_cells = (long long)s.band_count + s.band_fail;
   st->seeded = s.seeded;
-  st->probe_fail = s.probe_fail;
+  st->probe_fail = s.band_fail;
   st->nonphysical = s.nonphys;
   st->first_bad = s.nonphys ? s.first_bad : -1;
   int rc = check_launch();
   if (rc) return rc;
   if (s.nonphys) return fail(RBDI_ERR_NONPHYSICAL, "a cell left the admissible set");
+  if (s.band_count > h->task_cap) return fail(RBDI_ERR_OOM, "rigid band exceeds the seeding task capacity");
   return RBDI_OK;
 }
 

@@ -24,20 +24,71 @@ constexpr int kOut = 58;       // cells updated per wavefront
 constexpr int kHalo = 3;
 constexpr int kWPB = 4;        // wavefronts per block in 2D/3D sweeps
 
-// Device-resident scalars of one instance.
+// Device-resident scalars of one instance. Per-step values live in two
+// slots indexed by the parity of the step: during step n (parity p) slot p
+// holds t_n and, once the first sweep of the step has reduced the CFL
+// partials, dt_n; that reduction also writes t_{n+1} into slot p^1, which
+// nothing else reads during step n.
 struct DevScalars {
-  double dt;          // dt of the step being executed
-  double t;           // time at the start of the step
+  double t[2];        // time at the start of the step of each parity
+  double dtv[2];      // dt of the step of each parity
   double t_motion;    // time at which the rigid centre was set
   double last_dt;
   long long steps;
-  long long band_cells;
   long long seeded;
-  long long probe_fail;
   long long first_bad;
   int nonphys;
-  int band_count;
+  int band_count;     // seeding tasks of the current band
+  int band_fail;      // band cells without a valid probe
 };
+
+// Host-side arguments of one step.
+struct StepArgs {
+  int par;          // parity of the step
+  int npart;        // CFL partials to reduce (written by the previous step)
+  double cfl;       // CFL number (device dt)
+  double t_end;     // clip time (<= 0: none)
+  double dt_fixed;  // > 0: use this dt instead of the CFL value
+};
+
+// A step at or after t_end does no work.
+__device__ inline bool step_done(const DevScalars* sc, const StepArgs& a) {
+  if (a.dt_fixed > 0.0 || !(a.t_end > 0.0)) return false;
+  return !(a.t_end - sc->t[a.par] > 1e-14 * a.t_end);
+}
+
+// dt of the step: the fixed value, or cfl divided by the maximum of the CFL
+// partials (max over fluid cells and directions of max(|u_d| + c, |v_r,d|) /
+// dx_d), clipped at t_end; 0 (no work) once t_end is reached or when no
+// fluid cell exists. Run by one whole block (a max is exact and order
+// independent), which also does the step bookkeeping.
+__device__ inline void reduce_dt(DevScalars* sc, const double* __restrict__ part, const StepArgs& a) {
+  __shared__ double sh[16];
+  double m = 0.0;
+  if (!(a.dt_fixed > 0.0))
+    for (int q = threadIdx.x; q < a.npart; q += blockDim.x) m = fmax(m, part[q]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, sh[q]);
+    double dt = a.dt_fixed > 0.0 ? a.dt_fixed : (m > 0.0 ? a.cfl / m : 0.0);
+    if (step_done(sc, a)) dt = 0.0;
+    else if (a.t_end > 0.0 && !(a.dt_fixed > 0.0) && dt > a.t_end - sc->t[a.par]) dt = a.t_end - sc->t[a.par];
+    if (!(dt < 1e299)) dt = 0.0;
+    sc->dtv[a.par] = dt;
+    sc->t[a.par ^ 1] = sc->t[a.par] + dt;
+    if (dt > 0.0) {
+      sc->steps += 1;
+      sc->last_dt = dt;
+    }
+  }
+}
+
+// Single-block reduction kernel (used when no sweep precedes the one that
+// needs dt: 1D systems).
+__global__ void k_reduce_dt(DevScalars* sc, const double* __restrict__ part, StepArgs a) { reduce_dt(sc, part, a); }
 
 template <typename T>
 __device__ inline T shup(T v) { return __shfl_up(v, 1); }
@@ -110,37 +161,43 @@ __device__ inline double r_at(const Params& P, const T* __restrict__ U, int i, i
 }
 
 // ---------------------------------------------------------------------------
-// Direction sweep of one RK stage.
-// MODE 0: write this direction's contribution to D; 1: add it to D;
-// 2: final sweep -- total D, RK combine U_out = U^n + b (U_in - dt D - U^n)
-//    (b = 1, 1/4, 2/3; Sec. 3.1), rigid freeze, solid sources, admissibility.
+// Direction sweeps of one RK stage.
 // ---------------------------------------------------------------------------
-template <class S, typename T, int DIR, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
-                                              T* __restrict__ Dacc, T* __restrict__ Uout,
-                                              DevScalars* __restrict__ sc, double bcoef, int stage) {
-  const double dt = sc->dt;
-  if (dt == 0.0) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
-  int i, j, k, seg;
-  if (DIR == 0) { seg = blockIdx.x; j = blockIdx.y * wpb + wave; k = blockIdx.z; i = 0; if (j >= P.n[1]) return; }
-  else if (DIR == 1) { i = blockIdx.x * wpb + wave; seg = blockIdx.y; k = blockIdx.z; j = 0; if (i >= P.n[0]) return; }
-  else { i = blockIdx.x * wpb + wave; j = blockIdx.y; seg = blockIdx.z; k = 0; if (i >= P.n[0]) return; }
-  const int nd = P.n[DIR];
-  const int pos = seg * kOut - kHalo + lane;
-  const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
-  int pc[3] = {i, j, k};
-  pc[DIR] = posl;
 
+// CFL signal rate of one cell: max_d max(|u_d| + c, |v_r,d|) / dx_d
+// (dt = cfl / max over fluid cells; mixture sound speed of Sec. 2.2).
+template <class S, typename T>
+__device__ inline double cfl_rate(const Params& P, const T* Uc, const double* x, double tc) {
   T W[S::NF];
-  load_prim<S, T, DIR>(P, Uin, pc[0], pc[1], pc[2], W);
+  double J2 = 0.0;
+  cons_to_prim<S>(P, Uc, W, nullptr, &J2);
+  double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
+  phases_w<S>(W, phi, rl);
+  mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
+  const double cs = sqrt(c2);
+  double xs[3], v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xs[a] = x[a] - P.vr[a] * tc;
+  rigid_velocity(P, xs, v);
+  double m = 0.0;
+#pragma unroll
+  for (int d = 0; d < S::D; ++d) m = fmax(m, fmax(fabs((double)W[S::wU(d)]) + cs, fabs(v[d])) * P.inv_dx[d]);
+  return m;
+}
 
-  // MUSCL-BVD-THINC per variable (Sec. 3.1)
+// The per-cell work of a sweep along DIR on a wavefront whose lanes hold 64
+// consecutive cells (lane order = position order): MUSCL-BVD-THINC of every
+// primitive (Sec. 3.1; r skipped when it never changes, its flux being zero
+// then), first-order fallback of inadmissible cells, HLLC at the face to
+// the right of each cell, the upwind r flux, and this direction's part of
+// D = (F_+ - F_-)/dx - s_non-con (Sec. 3.1) for the cell. All lanes execute
+// it (cross-lane shuffles); only lanes 3..60 get a complete d.
+template <class S, typename T, int DIR>
+__device__ inline void sweep_core(const Params& P, const T* W, int pos, const int* pc, double tc, T* d) {
   T sL[S::NF], sR[S::NF];
 #pragma unroll
   for (int q = 0; q < S::NF; ++q) {
+    if (q == S::R && P.r_static) { sL[q] = W[q]; sR[q] = W[q]; continue; }
     const T wm = shup(W[q]), wp = shdn(W[q]);
     const Cand<T> c = candidates(P, wm, W[q], wp);
     const T lmR = shup(c.mR), ltR = shup(c.tR);
@@ -158,25 +215,18 @@ __global__ __launch_bounds__(256) void k_sweep(Params P, const T* __restrict__ U
   for (int q = 0; q < S::NF; ++q) WR[q] = shdn(sL[q]);
   T F[S::NT], us, Vs[3] = {T(0), T(0), T(0)};
   hllc<S, DIR>(P, sR, WR, F, us, Vs);
-  // rigid velocity at the face and the upwind r flux (Sec. 3.1)
-  double xf[3];
+  T vf = T(0), rfl = T(0);
+  if (!P.r_static) {
+    double xf[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) xf[a] = a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0;
-  xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR];
-  double vface;
-  {
-    double xs[3];
-    const double tc = sc->t - sc->t_motion;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xs[a] = xf[a] - P.vr[a] * tc;  // position relative to the moving centre
+    for (int a = 0; a < 3; ++a) xf[a] = (a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0) - P.vr[a] * tc;
+    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR] - P.vr[DIR] * tc;
     double v[3];
-    rigid_velocity(P, xs, v);
-    vface = v[DIR];
+    rigid_velocity(P, xf, v);
+    vf = (T)v[DIR];
+    rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
   }
-  const T vf = (T)vface;
-  const T rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
-
-  // left face of this cell from the previous lane
+  // the left face of this cell is the previous lane's right face
   T Fm[S::NT];
 #pragma unroll
   for (int q = 0; q < S::NT; ++q) Fm[q] = shup(F[q]);
@@ -184,11 +234,7 @@ __global__ __launch_bounds__(256) void k_sweep(Params P, const T* __restrict__ U
   T Vsm[3];
 #pragma unroll
   for (int b = 0; b < 3; ++b) Vsm[b] = shup(Vs[b]);
-
-  const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
-  if (!outlane) return;
   const T inv = (T)P.inv_dx[DIR];
-  T d[S::NF];
 #pragma unroll
   for (int q = 0; q < S::NT; ++q) d[q] = (F[q] - Fm[q]) * inv;
   const T du = us - usm;
@@ -204,49 +250,206 @@ __global__ __launch_bounds__(256) void k_sweep(Params P, const T* __restrict__ U
     }
   }
   d[S::R] = ((rfl - rflm) - W[S::R] * (vf - vfm)) * inv;
+}
 
-  const long long c = cell_index(P, pc[0], pc[1], pc[2]);
-  if (MODE == 0) {
+// Mirror / Dirichlet treatment of a primitive loaded for a ghost position.
+template <class S, typename T, int DIR>
+__device__ inline void ghost_fix(const Params& P, int mode, int face, T* W) {
+  if (mode == 2) {
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) Dacc[q * P.fs + c] = d[q];
-    return;
-  }
-  if (MODE == 1) {
+    for (int q = 0; q < S::NF; ++q) W[q] = (T)P.bcW[face][q];
+  } else if (mode == 1) {
+    W[S::wU(DIR)] = -W[S::wU(DIR)];
+    if constexpr (S::S) {
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) Dacc[q * P.fs + c] += d[q];
-    return;
-  }
-  if (S::D > 1) {
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) d[q] = Dacc[q * P.fs + c] + d[q];
-  }
-  const T dtt = (T)dt;
-  const T b = (T)bcoef;
-  const bool rigid = (double)U0[S::R * P.fs + c] > 0.5;
-  T Un[S::NF];
-#pragma unroll
-  for (int q = 0; q < S::NF; ++q) {
-    const T ui = Uin[q * P.fs + c];
-    const T ust = ui - dtt * d[q];
-    if (stage == 0) {
-      Un[q] = (rigid && q != S::R) ? ui : ust;
-    } else {
-      const T u0 = U0[q * P.fs + c];
-      Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
+        for (int b = 0; b < 3; ++b)
+          if ((a == DIR) != (b == DIR)) W[S::wV(a, b)] = -W[S::wV(a, b)];
     }
   }
-  if constexpr (S::S) {
-    if (!rigid) solid_sources<S>(P, Un);
+}
+
+// Final sweep (along x, coalesced): total D, RK combine
+// U_out = U^n + b (U_in - dt D - U^n) (b = 1, 1/4, 2/3; Sec. 3.1), rigid
+// freeze (Sec. 3.1), solid sources, admissibility flag; in the third stage
+// also one CFL partial per wavefront for the next step.
+template <class S>
+constexpr int sweep_max_threads() { return 256; }
+
+template <class S, typename T>
+__global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
+                                                const T* __restrict__ Dacc, T* __restrict__ Uout,
+                                                DevScalars* __restrict__ sc, double* __restrict__ cflpart,
+                                                StepArgs A, double bcoef, int stage) {
+  const double dt = sc->dtv[A.par];
+  if (dt == 0.0) return;  // uniform over the grid
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int seg = blockIdx.x, j = blockIdx.y * wpb + wave, k = blockIdx.z;
+  const size_t part_slot = (((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * wpb + wave;
+  if (j >= P.n[1]) {  // whole wavefront beyond the grid
+    if (stage == 2 && lane == 0) cflpart[part_slot] = 0.0;
+    return;
   }
-  bool ok = true;
-#pragma unroll
-  for (int l = 0; l < S::N; ++l) ok = ok && (Un[S::cA(l)] > T(0));
-  ok = ok && isfinite((double)Un[S::cE]);
-  if (!ok) {
-    if (atomicExch(&sc->nonphys, 1) == 0) sc->first_bad = c;
+  const int nd = P.n[0];
+  const int pos = seg * kOut - kHalo + lane;
+  const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
+  const int pc[3] = {posl, j, k};
+  const double tc = sc->t[A.par] - sc->t_motion;
+  T W[S::NF], Uc[S::NF];  // Uc: this lane's U_in, reused by the combine
+  {
+    int src, face;
+    const int mode = ghost_map(P, 0, posl, src, face);
+    if (mode != 2) {
+      load_cons<S>(P, Uin, cell_index(P, src, j, k), Uc);
+      cons_to_prim<S>(P, Uc, W);
+    }
+    ghost_fix<S, T, 0>(P, mode, face, W);
   }
+  T d[S::NF];
+  sweep_core<S, T, 0>(P, W, pos, pc, tc, d);
+  const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
+  double rate = 0.0;
+  if (outlane) {
+    const long long c = cell_index(P, pos, j, k);
+    if (S::D > 1) {
 #pragma unroll
-  for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = Un[q];
+      for (int q = 0; q < S::NF; ++q) d[q] = Dacc[q * P.fs + c] + d[q];
+    }
+    const T dtt = (T)dt;
+    const T b = (T)bcoef;
+    const bool rigid = (double)U0[S::R * P.fs + c] > 0.5;
+    T Un[S::NF];
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) {
+      const T ui = Uc[q];  // an output lane is an interior cell: its own load
+      const T ust = ui - dtt * d[q];
+      if (stage == 0) {
+        Un[q] = (rigid && q != S::R) ? ui : ust;
+      } else {
+        const T u0 = U0[q * P.fs + c];
+        Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
+      }
+    }
+    if constexpr (S::S) {
+      if (!rigid) solid_sources<S>(P, Un);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int l = 0; l < S::N; ++l) ok = ok && (Un[S::cA(l)] > T(0));
+    ok = ok && isfinite((double)Un[S::cE]);
+    if (!ok) {
+      if (atomicExch(&sc->nonphys, 1) == 0) sc->first_bad = c;
+    }
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = Un[q];
+    if (stage == 2 && !((double)Un[S::R] > 0.5)) {
+      double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pc[a] + 0.5) * P.dx[a];
+      x[0] = P.x0[0] + (pos + 0.5) * P.dx[0];
+      rate = cfl_rate<S>(P, Un, x, tc + dt);
+    }
+  }
+  if (stage == 2) {
+    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
+    if (lane == 0) cflpart[part_slot] = rate;
+  }
+}
+
+// Sweeps along y and z (not final): a block stages a tile of kTC columns x
+// 64 positions along DIR of U_in in LDS with coalesced loads (rows of kTC
+// consecutive x), each wavefront then runs the sweep on one column at a time
+// with lanes along DIR, writes its d back into the tile column, and the block
+// stores the tile coalesced into D (MODE 0: D = d; MODE 1: D += d).
+// REDUCE: the first sweep of a step; its block (0,0,0) also reduces the CFL
+// partials into the step's dt (this sweep itself does not use dt).
+constexpr int kRS = 65;  // LDS stride of a tile column (padded)
+
+template <class S, typename T>
+constexpr int tile_cols() {
+  return (S::NF * 16 * kRS * (int)sizeof(T) <= 48 * 1024) ? 16
+       : (S::NF * 8 * kRS * (int)sizeof(T) <= 48 * 1024) ? 8 : 4;
+}
+
+template <class S, typename T, int DIR, int MODE, bool REDUCE>
+__global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+                                                   DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
+                                                   StepArgs A) {
+  constexpr int TC = tile_cols<S, T>();
+  __shared__ T tile[S::NF * TC * kRS];
+  if constexpr (REDUCE) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) reduce_dt(sc, cflpart, A);
+    if (step_done(sc, A)) return;  // uniform over the grid
+  } else {
+    if (sc->dtv[A.par] == 0.0) return;  // uniform over the grid
+  }
+  const int x0 = blockIdx.x * TC;
+  int seg, j, k;
+  if (DIR == 1) { seg = blockIdx.y; k = blockIdx.z; j = 0; }
+  else { j = blockIdx.y; seg = blockIdx.z; k = 0; }
+  const int nd = P.n[DIR];
+  const int base = seg * kOut - kHalo;
+  for (int e = threadIdx.x; e < TC * kWave; e += blockDim.x) {
+    const int c = e % TC, r = e / TC;
+    const int x = x0 + c;
+    if (x >= P.n[0]) continue;
+    const int pos = base + r;
+    const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
+    int src, face;
+    if (ghost_map(P, DIR, posl, src, face) == 2) continue;
+    int p3[3] = {x, j, k};
+    p3[DIR] = src;
+    const long long cell = cell_index(P, p3[0], p3[1], p3[2]);
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + r] = Uin[q * P.fs + cell];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const double tc = sc->t[A.par] - sc->t_motion;
+  for (int c = wave; c < TC; c += blockDim.x / kWave) {
+    const int x = x0 + c;
+    if (x >= P.n[0]) break;  // uniform in the wavefront
+    const int pos = base + lane;
+    const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
+    int pc[3] = {x, j, k};
+    pc[DIR] = posl;
+    T W[S::NF];
+    int src, face;
+    const int mode = ghost_map(P, DIR, posl, src, face);
+    if (mode != 2) {
+      T Uc[S::NF];
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) Uc[q] = tile[(q * TC + c) * kRS + lane];
+      cons_to_prim<S>(P, Uc, W);
+    }
+    ghost_fix<S, T, DIR>(P, mode, face, W);
+    T d[S::NF];
+    sweep_core<S, T, DIR>(P, W, pos, pc, tc, d);
+    if (lane >= kHalo && lane < kHalo + kOut && pos < nd) {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + lane] = d[q];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TC * kWave; e += blockDim.x) {
+    const int c = e % TC, r = e / TC;
+    const int x = x0 + c;
+    const int pos = base + r;
+    if (x >= P.n[0] || r < kHalo || r >= kHalo + kOut || pos >= nd) continue;
+    int p3[3] = {x, j, k};
+    p3[DIR] = pos;
+    const long long cell = cell_index(P, p3[0], p3[1], p3[2]);
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) {
+      const T v = tile[(q * TC + c) * kRS + r];
+      if (MODE == 0) Dacc[q * P.fs + cell] = v;
+      else Dacc[q * P.fs + cell] += v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -275,70 +478,109 @@ __device__ inline bool youngs_normal(const Params& P, const T* __restrict__ U, i
   return true;
 }
 
+// Seeding geometry of one rigid cell (Sec. 3.2 steps 1-2): Youngs normal,
+// probe along n at 1, 1.5, ..., 4 dx (or the fixed 1.5 dx); the first point
+// whose enclosing cells with a nonzero interpolation weight are all interior
+// with r <= 0.5 is used. It depends on r only, so for a static body it is
+// computed once and reused by every step.
+struct SeedTask {
+  int c;          // linear index of the rigid cell
+  int lo[3];      // lower corner of the interpolation support
+  double w[3];    // multilinear weights
+  double n[3];    // outward normal
+};
+
 template <class S, typename T>
-__global__ __launch_bounds__(256) void k_band(Params P, const T* __restrict__ U, int* __restrict__ band,
-                                             DevScalars* __restrict__ sc) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.ncell || sc->dt == 0.0) return;
-  if (!((double)U[S::R * P.fs + c] > 0.5)) return;
-  int i, j, k;
-  decode(P, c, i, j, k);
-  double n[3];
-  if (!youngs_normal<S>(P, U, i, j, k, n)) return;
-  const int slot = atomicAdd(&sc->band_count, 1);
-  band[slot] = (int)c;
+__device__ inline bool probe_ok(const Params& P, const T* __restrict__ U, const int* lo, const double* w) {
+  bool ok = true;
+#pragma unroll
+  for (int cb = 0; cb < (1 << S::D); ++cb) {
+    int cp[3] = {0, 0, 0};
+    bool used = true, inside = true;
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) {
+      const int bit = (cb >> a) & 1;
+      if (bit && w[a] == 0.0) used = false;
+      cp[a] = lo[a] + bit;
+      inside = inside && cp[a] >= 0 && cp[a] < P.n[a];
+    }
+    if (used) {
+      if (!inside) ok = false;
+      else if (!((double)U[S::R * P.fs + cell_index(P, cp[0], cp[1], cp[2])] <= 0.5)) ok = false;
+    }
+  }
+  return ok;
 }
 
-// Seeding of every band cell: probe along n at 1, 1.5, ..., 4 dx (or the
-// fixed 1.5 dx), first point whose nonzero-weight enclosing cells are all
-// interior with r <= 0.5, multilinear interpolation of primitives (nested
-// linear interpolations), mirror state, optional Riemann star state, write
-// the thermodynamic fields. Support cells are never rigid, so cells seeded
-// by other threads are never read.
 template <class S, typename T>
-__global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const int* __restrict__ band,
-                                             DevScalars* __restrict__ sc) {
-  if (sc->dt == 0.0) return;  // a step after t_end does no work
-  const int nb = sc->band_count;
-  int nfail = 0, nseed = 0;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-    const long long c = band[b];
-    int pi[3];
-    decode(P, c, pi[0], pi[1], pi[2]);
-    double n[3];
-    if (!youngs_normal<S>(P, U, pi[0], pi[1], pi[2], n)) continue;
-    const int nprobe = P.probe == PROBE_FIXED ? 1 : 7;
-    int lo[3] = {0, 0, 0};
-    double w[3] = {0.0, 0.0, 0.0};
-    bool found = false;
-    for (int pr = 0; pr < nprobe && !found; ++pr) {
+__global__ __launch_bounds__(256) void k_band(Params P, const T* __restrict__ U, SeedTask* __restrict__ tasks,
+                                             int cap, DevScalars* __restrict__ sc, StepArgs A) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (step_done(sc, A)) return;
+  if (c >= P.ncell) return;
+  if (!((double)U[S::R * P.fs + c] > 0.5)) return;
+  int pi[3];
+  decode(P, c, pi[0], pi[1], pi[2]);
+  double n[3];
+  if (!youngs_normal<S>(P, U, pi[0], pi[1], pi[2], n)) return;
+  const int nprobe = P.probe == PROBE_FIXED ? 1 : 7;
+  int best = -1;
+  int blo[3] = {0, 0, 0};
+  double bw[3] = {0.0, 0.0, 0.0};
+  // all probe distances are tested independently (their loads overlap);
+  // the first valid one wins
+#pragma unroll
+  for (int pr = 0; pr < 7; ++pr) {
+    if (pr < nprobe) {
       const double dist = P.probe == PROBE_FIXED ? 1.5 : 1.0 + 0.5 * pr;
+      int lo[3] = {0, 0, 0};
+      double w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < S::D; ++a) {
         const double xi = pi[a] + dist * n[a] * (P.dmin * P.inv_dx[a]);
         lo[a] = (int)floor(xi);
         w[a] = xi - lo[a];
       }
-      bool ok = true;
+      if (probe_ok<S>(P, U, lo, w) && best < 0) {
+        best = pr;
 #pragma unroll
-      for (int cb = 0; cb < (1 << S::D); ++cb) {
-        int cp[3] = {0, 0, 0};
-        bool used = true;
-#pragma unroll
-        for (int a = 0; a < S::D; ++a) {
-          const int bit = (cb >> a) & 1;
-          if (bit && w[a] == 0.0) used = false;
-          cp[a] = lo[a] + bit;
-        }
-        if (!used || !ok) continue;
-#pragma unroll
-        for (int a = 0; a < S::D; ++a) ok = ok && cp[a] >= 0 && cp[a] < P.n[a];
-        if (ok) ok = (double)U[S::R * P.fs + cell_index(P, cp[0], cp[1], cp[2])] <= 0.5;
+        for (int a = 0; a < 3; ++a) { blo[a] = lo[a]; bw[a] = w[a]; }
       }
-      found = ok;
     }
-    if (!found) { ++nfail; continue; }
-    // primitives at the support corners
+  }
+  if (best < 0) {
+    atomicAdd(&sc->band_fail, 1);
+    return;
+  }
+  const int slot = atomicAdd(&sc->band_count, 1);
+  if (slot >= cap) return;  // reported by rbdi_status
+  SeedTask t;
+  t.c = (int)c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) { t.lo[a] = blo[a]; t.w[a] = bw[a]; t.n[a] = n[a]; }
+  tasks[slot] = t;
+}
+
+__global__ void k_band_reset(DevScalars* sc, StepArgs A) {
+  if (step_done(sc, A)) return;
+  sc->band_count = 0;
+  sc->band_fail = 0;
+}
+
+// Seeding states (Sec. 3.2 steps 3-5): multilinear interpolation of the
+// primitives at the probe (nested linear interpolations), mirror state,
+// optional Riemann star state, written to the thermodynamic fields of the
+// rigid cell. Support cells are never rigid, so no thread reads a cell that
+// another one writes.
+template <class S, typename T>
+__global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const SeedTask* __restrict__ tasks,
+                                             int cap, DevScalars* __restrict__ sc, StepArgs A) {
+  if (step_done(sc, A)) return;
+  const int nb = sc->band_count < cap ? sc->band_count : cap;
+  const double tc = sc->t[A.par] - sc->t_motion;
+  int nseed = 0;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const SeedTask t = tasks[b];
     double Wc[1 << S::D][S::NF];
 #pragma unroll
     for (int cb = 0; cb < (1 << S::D); ++cb) {
@@ -346,7 +588,7 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
 #pragma unroll
       for (int a = 0; a < S::D; ++a) {
         const int bit = (cb >> a) & 1;
-        cp[a] = lo[a] + ((bit && w[a] != 0.0) ? 1 : 0);
+        cp[a] = t.lo[a] + ((bit && t.w[a] != 0.0) ? 1 : 0);
       }
       T Uc[S::NF], Wt[S::NF];
       load_cons<S>(P, U, cell_index(P, cp[0], cp[1], cp[2]), Uc);
@@ -358,13 +600,15 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
 #pragma unroll
     for (int a = 0; a < S::D; ++a) {
       m >>= 1;
+#pragma unroll
       for (int cb = 0; cb < m; ++cb)
 #pragma unroll
         for (int q = 0; q < S::NF; ++q)
-          Wc[cb][q] = Wc[2 * cb][q] + w[a] * (Wc[2 * cb + 1][q] - Wc[2 * cb][q]);
+          Wc[cb][q] = Wc[2 * cb][q] + t.w[a] * (Wc[2 * cb + 1][q] - Wc[2 * cb][q]);
     }
+    int pi[3];
+    decode(P, t.c, pi[0], pi[1], pi[2]);
     double xc[3] = {0.0, 0.0, 0.0};
-    const double tc = sc->t - sc->t_motion;
 #pragma unroll
     for (int a = 0; a < S::D; ++a) xc[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
 #pragma unroll
@@ -372,8 +616,8 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
     double v[3];
     rigid_velocity(P, xc, v);
     double Wm[S::NF], Wg[S::NF];
-    mirror<S>(Wc[0], n, v, Wm);
-    if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], n, Wg);
+    mirror<S>(Wc[0], t.n, v, Wm);
+    if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], t.n, Wg);
     else {
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) Wg[q] = Wm[q];
@@ -381,13 +625,12 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
     T Wt[S::NF], Ug[S::NF];
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) Wt[q] = (T)Wg[q];
-    Wt[S::R] = U[S::R * P.fs + c];
+    Wt[S::R] = U[S::R * P.fs + t.c];
     prim_to_cons<S>(P, Wt, Ug);
 #pragma unroll
-    for (int q = 0; q < S::NT; ++q) U[q * P.fs + c] = Ug[q];
+    for (int q = 0; q < S::NT; ++q) U[q * P.fs + t.c] = Ug[q];
     ++nseed;
   }
-  if (nfail) atomicAdd((unsigned long long*)&sc->probe_fail, (unsigned long long)nfail);
   if (nseed) atomicAdd((unsigned long long*)&sc->seeded, (unsigned long long)nseed);
 }
 
@@ -426,79 +669,38 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// CFL candidate of each non-rigid cell: min_d dx_d / max(|u_d| + c, |v_r,d|).
+// CFL partials (one per block) of the current state, for a state that did
+// not come from a step; the first sweep of the next step reduces them.
 template <class S, typename T>
-__global__ __launch_bounds__(kRedThreads) void k_dt_partial(Params P, const T* __restrict__ U,
-                                                           const DevScalars* __restrict__ sc,
-                                                           double* __restrict__ part) {
+__global__ __launch_bounds__(kRedThreads) void k_cfl(Params P, const T* __restrict__ U,
+                                                    const DevScalars* __restrict__ sc, int par,
+                                                    double* __restrict__ part) {
   __shared__ double sh[kRedThreads / 64];
-  double m = 1e300;
-  const double tc = sc->t - sc->t_motion;
+  double m = 0.0;
+  const double tc = sc->t[par] - sc->t_motion;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
        c += (long long)gridDim.x * blockDim.x) {
     if ((double)U[S::R * P.fs + c] > 0.5) continue;
-    T Uc[S::NF], W[S::NF];
+    T Uc[S::NF];
     load_cons<S>(P, U, c, Uc);
-    double J2 = 0.0;
-    cons_to_prim<S>(P, Uc, W, nullptr, &J2);
-    double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
-    phases_w<S>(W, phi, rl);
-    mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
-    const double cs = sqrt(c2);
     int pi[3];
     decode(P, c, pi[0], pi[1], pi[2]);
     double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] -= P.vr[a] * tc;
-    double v[3];
-    rigid_velocity(P, x, v);
-#pragma unroll
-    for (int d = 0; d < S::D; ++d) {
-      const double s = fmax(fabs((double)W[S::wU(d)]) + cs, fabs(v[d]));
-      m = fmin(m, P.dx[d] / s);
-    }
+    m = fmax(m, cfl_rate<S>(P, Uc, x, tc));
   }
-  m = block_min(m, sh);
+  m = -block_min(-m, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
-// dt = cfl * min, clipped at t_end (t_end <= 0: no clip); dt = 0 once t_end
-// is reached (the step then does no work).
-__global__ void k_dt_final(const double* __restrict__ part, int nparts, double cfl, double t_end,
-                           DevScalars* __restrict__ sc, double* __restrict__ out) {
+// Maximum of n partials (for rbdi_compute_dt).
+__global__ void k_max_partials(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sh[4];
-  double m = 1e300;
-  for (int q = threadIdx.x; q < nparts; q += blockDim.x) m = fmin(m, part[q]);
-  m = block_min(m, sh);
-  if (threadIdx.x == 0) {
-    double dt = cfl * m;
-    if (t_end > 0.0) {
-      const double rem = t_end - sc->t;
-      if (!(rem > 1e-14 * t_end)) dt = 0.0;
-      else if (dt > rem) dt = rem;
-    }
-    if (out) *out = dt;
-    else sc->dt = dt;
-  }
-}
-
-__global__ void k_set_dt(DevScalars* sc, double dt) { sc->dt = dt; }
-
-__global__ void k_end_step(DevScalars* sc) {
-  const double dt = sc->dt;
-  if (dt == 0.0) return;
-  sc->t += dt;
-  sc->last_dt = dt;
-  sc->steps += 1;
-}
-
-__global__ void k_reset_band(DevScalars* sc) {
-  if (sc->dt != 0.0) sc->band_count = 0;
-}
-__global__ void k_band_stat(DevScalars* sc) {
-  if (sc->dt != 0.0) sc->band_cells = sc->band_count;
+  double m = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) m = fmax(m, part[q]);
+  m = -block_min(-m, sh);
+  if (threadIdx.x == 0) *out = m;
 }
 
 // Force and torque: per cell f = -sigma . grad_h r dV, torque (x - c) x f.

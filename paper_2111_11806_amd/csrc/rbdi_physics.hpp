@@ -22,6 +22,18 @@ enum { RS_HLLC = 0, RS_HLLC_LM = 1 };
 enum { SEED_ORIGINAL = 0, SEED_RIEMANN = 1, SEED_NONE = 2 };
 enum { PROBE_STEPOUT = 0, PROBE_FIXED = 1 };
 
+// Reciprocal from the hardware estimate refined by two Newton steps (FP64;
+// within an ulp or two of 1/x), or the single-precision hardware
+// reciprocal. Used only where x is finite and nonzero.
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Material constants in the form the device closure uses.
 struct MatDev {
   int kind;
@@ -30,6 +42,7 @@ struct MatDev {
   double Bfl;           // fluids: rho e_ref - p_ref / Gamma = gamma p_inf / Gamma
   double rho0, invrho0, K0, G0, alpha, beta, kc;  // Romenskii, kc = K0 / (2 alpha^2)
   double sigY;
+  double gGam;          // fluids: gamma / Gamma (sound-speed weight)
 };
 
 // Launch-invariant parameters of one instance (passed by value).
@@ -45,6 +58,7 @@ struct Params {
   double cosh_b, inv_sinh_b, tanh_b, beta;
   double lm_mach;
   int solid_phase;
+  int r_static;           // rigid velocity identically zero: r never changes
   MatDev mat[kMaxMat];
   double vr[3], om[3], ctr[3];
   double bcW[6][kMaxF];   // Dirichlet primitive states per face
@@ -182,6 +196,7 @@ __device__ inline void romenskii_ref(const MatDev& m, double rho, double J2, dou
 template <class S>
 __device__ inline double mix_pressure(const Params& P, const double* phi, const double* rho, double J2,
                                       double rhoe) {
+  if constexpr (S::N == 1 && !S::S) return (rhoe - P.mat[0].Bfl) * P.mat[0].Gam;
   double num = rhoe, den = 0.0;
 #pragma unroll
   for (int l = 0; l < S::N; ++l) {
@@ -195,7 +210,7 @@ __device__ inline double mix_pressure(const Params& P, const double* phi, const 
     num -= phi[l] * B;
     den += phi[l] * m.invGam;
   }
-  return num / den;
+  return num * frcp(den);
 }
 
 // rho e from p (the same isobaric relation solved for rho e).
@@ -222,6 +237,24 @@ __device__ inline double mix_rhoe(const Params& P, const double* phi, const doub
 template <class S>
 __device__ inline void mix_c2_G(const Params& P, const double* phi, const double* rho, double J2, double p,
                                 double& c2, double& G, double& sigY) {
+  if constexpr (!S::S) {
+    // fluids: Y_l c_l^2 = phi_l gamma_l (p + p_inf,l) / rho
+    G = 0.0;
+    sigY = 0.0;
+    if constexpr (S::N == 1) {
+      c2 = P.mat[0].gamma * (p + P.mat[0].pinf) * frcp(rho[0]);
+    } else {
+      double num = 0.0, den = 0.0, rhom = 0.0;
+#pragma unroll
+      for (int l = 0; l < S::N; ++l) {
+        num += phi[l] * P.mat[l].gGam * (p + P.mat[l].pinf);
+        den += phi[l] * P.mat[l].invGam;
+        rhom += phi[l] * rho[l];
+      }
+      c2 = num * frcp(rhom * den);
+    }
+    return;
+  }
   double rhom = 0.0;
 #pragma unroll
   for (int l = 0; l < S::N; ++l) rhom += phi[l] * rho[l];
@@ -278,9 +311,13 @@ __device__ inline void cons_to_prim(const Params& P, const T* U, T* W, double* H
     s += phi[l];
   }
   phi[S::N - 1] = 1.0 - s;
+  if constexpr (S::N == 1) {
+    rl[0] = (double)U[S::cA(0)];
+  } else {
 #pragma unroll
-  for (int l = 0; l < S::N; ++l) rl[l] = (double)U[S::cA(l)] / phi[l];
-  const double inv = 1.0 / rho;
+    for (int l = 0; l < S::N; ++l) rl[l] = (double)U[S::cA(l)] * frcp(phi[l]);
+  }
+  const double inv = frcp(rho);
   double ke = 0.0;
 #pragma unroll
   for (int a = 0; a < S::D; ++a) {
@@ -390,7 +427,7 @@ __device__ inline Cand<T> candidates(const Params& P, T qm, T q0, T qp) {
   const T a = qp - q0, b = q0 - qm;
   const T ab = a * b;
   T half_slope = T(0);
-  if (ab > T(0)) half_slope = ab / (a + b);
+  if (ab > T(0)) half_slope = ab * frcp(a + b);
   c.mL = q0 - half_slope;
   c.mR = q0 + half_slope;
   c.tL = c.mL;
@@ -399,13 +436,13 @@ __device__ inline Cand<T> candidates(const Params& P, T qm, T q0, T qp) {
     const T qmin = qm < qp ? qm : qp;
     const T dq = fabs(qp - qm);
     const T th = qp > qm ? T(1) : T(-1);
-    const T C = (q0 - qmin) / dq;
+    const T C = (q0 - qmin) * frcp(dq);
     const T e = exp(th * T(P.beta) * (T(2) * C - T(1)));
     const T tt = (T(P.cosh_b) - e) * T(P.inv_sinh_b);
     const T tb = T(P.tanh_b);
     const T hd = T(0.5) * dq;
     c.tL = qmin + hd * (T(1) - th * tt);
-    c.tR = qmin + hd * (T(1) + th * (tb - tt) / (T(1) - tb * tt));
+    c.tR = qmin + hd * (T(1) + th * (tb - tt) * frcp(T(1) - tb * tt));
   }
   return c;
 }
@@ -493,7 +530,7 @@ __device__ inline void field_terms(const T* W, const SideState<S>& s, int q, int
 #pragma unroll
     for (int a = 0; a < 3; ++a) work += s.u[a] * s.sig[a];
     f = s.E * un - work;
-    us = chi * (s.E + (Ss - un) * (s.rho * Ss + s.P / (Sk - un)));
+    us = chi * (s.E + (Ss - un) * (s.rho * Ss + s.P * frcp(Sk - un)));
   } else if (q < S::cE + S::N) {  // phi_l
     u = (double)W[S::wPHI(q - S::cE - 1)];
     f = u * un;
@@ -524,17 +561,22 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
   const double SL = fmin(L.un - L.c, R.un - R.c);
   const double SR = fmax(L.un + L.c, R.un + R.c);
   const double mL = L.rho * (SL - L.un), mR = R.rho * (SR - R.un);
-  const double Ss = (R.P - L.P + L.un * mL - R.un * mR) / (mL - mR);
+  const double Ss = (R.P - L.P + L.un * mL - R.un * mR) * frcp(mL - mR);
   const int sp = P.solid_phase < 0 ? 0 : P.solid_phase;
   if (P.riemann == RS_HLLC_LM && SL < 0.0 && SR > 0.0) {
-    const double chiL = (SL - L.un) / (SL - Ss), chiR = (SR - R.un) / (SR - Ss);
+    const double chiL = (SL - L.un) * frcp(SL - Ss), chiR = (SR - R.un) * frcp(SR - Ss);
     double cnL = 1, ctL = 1, cnR = 1, ctR = 1;
     if constexpr (S::S) {
       ctL = cbrt(chiL); cnL = 1.0 / (ctL * ctL);
       ctR = cbrt(chiR); cnR = 1.0 / (ctR * ctR);
     }
-    const double Ma = fmax(fabs(L.un) / L.c, fabs(R.un) / R.c);
-    const double ph = sin(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
+    // acoustic scaling sin(min(1, Ma/Ma_lim) pi/2); 1 once either side
+    // reaches the limit
+    double ph = 1.0;
+    if (!(fabs(L.un) >= P.lm_mach * L.c || fabs(R.un) >= P.lm_mach * R.c)) {
+      const double Ma = fmax(fabs(L.un) * frcp(L.c), fabs(R.un) * frcp(R.c));
+      ph = sin(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
+    }
     const double aS = fabs(Ss);
 #pragma unroll
     for (int q = 0; q < S::NT; ++q) {
@@ -563,7 +605,7 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
   const SideState<S>& K = useL ? L : R;
   const T* WK = useL ? WL : WR;
   const double Sk = useL ? SL : SR;
-  const double chi = star ? (Sk - K.un) / (Sk - Ss) : 1.0;
+  const double chi = star ? (Sk - K.un) * frcp(Sk - Ss) : 1.0;
   double cn = 1.0, ct = 1.0;
   if constexpr (S::S) {
     if (star) { ct = cbrt(chi); cn = 1.0 / (ct * ct); }
