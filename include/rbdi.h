@@ -212,6 +212,25 @@ RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
 RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable);
 RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches);
 
+/* Unit-level evaluation of single device functions on n states (host
+ * arrays, FP64, state-major: n x nfields), for parity checks of the
+ * building blocks of the step. what = 0: HLLC flux along dir of the face
+ * (a[i] left primitive state, b[i] right), out n x (nfields + 3) = flux of
+ * the nfields-1 thermodynamic fields, wall velocity u*, wall stretch row
+ * Vbar*_{dir,0..2} (Sec. 3.1). what = 1: closure of conserved states a,
+ * out n x (nfields + 10) = primitives, mixture c^2, Cauchy stress (9)
+ * (Sec. 2.2). what = 2: per-stage elastoplastic sources of conserved states
+ * a, out n x nfields. Synchronises; allocates temporary device memory. */
+RBDI_API int rbdi_unit_eval(rbdi_handle* h, int what, int dir, const double* a, const double* b, double* out,
+                            int n);
+
+/* The semi-discrete operator D(U) of the current state (Sec. 3.1, spatial
+ * operator; no seeding; thermodynamic rows of rigid cells are not used by a
+ * step), host FP64 [nfields][cells], summed over the directions whose bit is
+ * set in dirmask (bit d = direction d; 7 = all). Diagnostic: overwrites the
+ * handle's stage buffers; synchronises. */
+RBDI_API int rbdi_eval_rhs(rbdi_handle* h, int dirmask, double* D);
+
 /* Message of the last error on the calling thread ("" if none). */
 RBDI_API const char* rbdi_last_error(void);
 

@@ -99,6 +99,7 @@ def lib():
             L.orc_compute_dt.argtypes = [vp, ctypes.c_double]
             L.orc_step.argtypes = [vp, ctypes.c_double]
             L.orc_seed.argtypes = [vp]
+            L.orc_rhs.argtypes = [vp, dp, ip]
             L.orc_time.restype = ctypes.c_double
             L.orc_time.argtypes = [vp]
             L.orc_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
@@ -218,6 +219,12 @@ class Oracle:
 
     def seed(self):
         lib().orc_seed(self._h)
+
+    def rhs(self, dirmask=7):
+        """D(U) of the current state (no seeding; rigid mask from r)."""
+        out = np.empty(self.shape)
+        lib().orc_rhs(self._h, _dp(out), int(dirmask))
+        return out
 
     @property
     def t(self):

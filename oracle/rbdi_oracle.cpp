@@ -613,18 +613,29 @@ struct Oracle {
       VsL[b] = L.solid ? UsL[L.V(d, b)] : 0.0;
       VsR[b] = L.solid ? UsR[L.V(d, b)] : 0.0;
     }
-    // Godunov state of the stretch row at x/t = 0
+    // Wall value of the stretch row: its state at x/t = 0 of the HLLC fan
+    // outside the star region; inside it, the star states weighted by the
+    // position of the contact in the fan, w = (S* - S_L)/(S_R - S_L), which
+    // is continuous in S* (the two star states differ across the contact).
     for (int b = 0; b < 3; ++b) {
       if (SL >= 0.0) Vstar[b] = VL[b];
-      else if (Ss >= 0.0) Vstar[b] = VsL[b];
-      else if (SR > 0.0) Vstar[b] = VsR[b];
-      else Vstar[b] = VR[b];
+      else if (SR <= 0.0) Vstar[b] = VR[b];
+      else Vstar[b] = VsR[b] + (Ss - SL) / (SR - SL) * (VsL[b] - VsR[b]);
     }
-    if (riemann == RS_HLLC_LM) {
+    // Reading (the paper's solid solver is HLLD, not given here): for the
+    // elastoplastic system the star states carry only the normal traction, so
+    // the Rankine-Hugoniot condition across the contact fails for the
+    // tangential traction and its work; the star-region flux is then taken
+    // in the central form (1/2)(F*_L + F*_R) + (1/2)|S*|(U*_L - U*_R), which
+    // equals Toro's flux where that condition holds and has no jump at S* = 0.
+    if (riemann == RS_HLLC_LM || L.solid) {
       if (SL >= 0.0) { for (int q = 0; q < nt; ++q) Fo[q] = FL[q]; ustar = uL; return; }
       if (SR <= 0.0) { for (int q = 0; q < nt; ++q) Fo[q] = FR[q]; ustar = uR; return; }
-      const double Ma = std::max(std::fabs(uL) / cL, std::fabs(uR) / cR);
-      const double ph = std::sin(std::min(1.0, Ma / lm_mach) * M_PI * 0.5);
+      double ph = 1.0;
+      if (riemann == RS_HLLC_LM) {
+        const double Ma = std::max(std::fabs(uL) / cL, std::fabs(uR) / cR);
+        ph = std::sin(std::min(1.0, Ma / lm_mach) * M_PI * 0.5);
+      }
       const double aS = std::fabs(Ss);
       for (int q = 0; q < nt; ++q)
         Fo[q] = 0.5 * (FL[q] + FR[q]) +
@@ -658,6 +669,7 @@ struct Oracle {
   // the reconstructed face values of r (Sec. 3.1).
   // Cells with r > 0.5 at the start of the step keep their thermodynamic
   // state (Sec. 3.1: not updated in rigid cells); only r is updated there.
+  int dirmask = 7;  // diagnostics: directions included in D
   void rhs(const std::vector<double>& Uin, const std::vector<unsigned char>& rigid,
            std::vector<double>& D) {
     std::vector<double> X = Uin;
@@ -668,6 +680,7 @@ struct Oracle {
     const int nv = L.n;
     long nfb = 0;
     for (int d = 0; d < dim; ++d) {
+      if (!((dirmask >> d) & 1)) continue;
       const size_t st = stride(d);
       // pencils along d: iterate over the interior of the other dimensions
       int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
@@ -1252,6 +1265,28 @@ ORC_API int orc_step(void* h, double dt) {
 }
 
 ORC_API int orc_seed(void* h) { static_cast<Oracle*>(h)->do_seed(); return 0; }
+
+// The semi-discrete operator D(U) of the current state (no seeding), rigid
+// mask from the current r: out [nfields][interior cells].
+ORC_API int orc_rhs(void* h, double* out, int dirmask) {
+  Oracle* o = static_cast<Oracle*>(h);
+  o->dirmask = dirmask;
+  std::vector<unsigned char> rigid(o->ncell, 0);
+  const double* r = o->f(o->L.R());
+  for (size_t c = 0; c < o->ncell; ++c) rigid[c] = r[c] > 0.5;
+  std::vector<double> D;
+  o->rhs(o->U, rigid, D);
+  const size_t ni = (size_t)o->nint();
+  for (size_t lin = 0; lin < ni; ++lin) {
+    const int i = (int)(lin % o->n[0]);
+    const int j = (int)((lin / o->n[0]) % o->n[1]);
+    const int k = (int)(lin / ((size_t)o->n[0] * o->n[1]));
+    const size_t c = o->idx(i, j, k);
+    for (int q = 0; q < o->L.n; ++q) out[(size_t)q * ni + lin] = D[(size_t)q * o->ncell + c];
+  }
+  o->dirmask = 7;
+  return 0;
+}
 
 ORC_API double orc_time(void* h) { return static_cast<Oracle*>(h)->t; }
 

@@ -109,6 +109,8 @@ struct Ops {
   void (*force)(rbdi_handle*, const double*);
   void (*totals)(rbdi_handle*);
   int (*part_blocks)(const Params&);
+  void (*unit)(rbdi_handle*, int, int, const double*, const double*, double*, int);
+  void (*rhs)(rbdi_handle*, int);
 };
 
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -215,9 +217,36 @@ struct Impl {
                        2 * S::NF, h->red_out);
   }
   static int part_blocks(const Params& P) { return std::max(x_partials(P), kRedBlocks); }
+  // D(U^n) into U[1] (rigid mask from r), for diagnostics
+  static void rhs(rbdi_handle* h, int dirmask) {
+    StepArgs A{};
+    A.par = h->par;
+    A.rhs_only = 1 | ((~dirmask & 7) << 1);
+    const T* U0 = u(h, 0);
+    if constexpr (S::D == 3) {
+      sweep_t<2, 0, false>(h, U0, A);
+      sweep_t<1, 1, false>(h, U0, A);
+    } else if constexpr (S::D == 2) {
+      sweep_t<1, 0, false>(h, U0, A);
+    }
+    sweep_x(h, U0, U0, u(h, 1), A, 1.0, 0);
+  }
+  // what: 0 face flux (dir), 1 closure, 2 solid sources
+  static void unit(rbdi_handle* h, int what, int dir, const double* a, const double* b, double* out, int n) {
+    const dim3 g((unsigned)((n + 63) / 64)), t(64);
+    if (what == 0) {
+      if (dir == 0) hipLaunchKernelGGL((k_unit_flux<S, T, 0>), g, t, 0, h->stream, h->P, a, b, out, n);
+      else if (dir == 1 && S::D > 1) hipLaunchKernelGGL((k_unit_flux<S, T, (S::D > 1 ? 1 : 0)>), g, t, 0, h->stream, h->P, a, b, out, n);
+      else if (dir == 2 && S::D > 2) hipLaunchKernelGGL((k_unit_flux<S, T, (S::D > 2 ? 2 : 0)>), g, t, 0, h->stream, h->P, a, b, out, n);
+    } else if (what == 1) {
+      hipLaunchKernelGGL((k_unit_closure<S, T>), g, t, 0, h->stream, h->P, a, out, n);
+    } else {
+      hipLaunchKernelGGL((k_unit_sources<S, T>), g, t, 0, h->stream, h->P, out, n);
+    }
+  }
   static const Ops* ops() {
     static const Ops o = {prim_to_state, state_to_prim, state_to_f64, f64_to_state, r_from_sdf, band, seed,
-                          stages, cfl, force, totals, part_blocks};
+                          stages, cfl, force, totals, part_blocks, unit, rhs};
     return &o;
   }
 };
@@ -529,7 +558,7 @@ RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const doub
 // step bookkeeping on the device.
 static void enqueue_step(rbdi_handle* h, double dt_fixed, double cfl, double t_end) {
   if (dt_fixed <= 0.0 && !h->cfl_valid) h->ops->cfl(h);
-  StepArgs A;
+  StepArgs A{};
   A.par = h->par;
   A.npart = h->npart;
   A.cfl = cfl;
@@ -580,6 +609,45 @@ RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end) 
   if (!(cfl > 0.0) || nsteps < 0) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 and nsteps >= 0");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
   for (int s = 0; s < nsteps; ++s) enqueue_step(h, 0.0, cfl, t_end);
+  return check_launch();
+}
+
+RBDI_API int rbdi_unit_eval(rbdi_handle* h, int what, int dir, const double* a, const double* b, double* out,
+                           int n) {
+  if (!h || !a || !out || n < 0 || what < 0 || what > 2) return fail(RBDI_ERR_BAD_ARG, "bad unit_eval argument");
+  if (what == 0 && (!b || dir < 0 || dir >= h->desc.dim)) return fail(RBDI_ERR_BAD_ARG, "bad flux direction");
+  if (n == 0) return RBDI_OK;
+  const int nf = h->nf, nt = nf - 1;
+  const size_t in_n = (size_t)n * nf;
+  const size_t out_n = (size_t)n * (what == 0 ? nt + 4 : (what == 1 ? nf + 10 : nf));
+  double *da = nullptr, *db = nullptr, *dout = nullptr;
+  HIP_OK(hipMalloc(&da, in_n * sizeof(double)));
+  HIP_OK(hipMalloc(&db, in_n * sizeof(double)));
+  HIP_OK(hipMalloc(&dout, out_n * sizeof(double)));
+  HIP_OK(hipMemcpyAsync(da, a, in_n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (what == 0) HIP_OK(hipMemcpyAsync(db, b, in_n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (what == 2) HIP_OK(hipMemcpyAsync(dout, a, in_n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  h->ops->unit(h, what, dir, da, db, dout, n);
+  HIP_OK(hipMemcpyAsync(out, dout, out_n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  int rc = check_launch();
+  (void)hipFree(da);
+  (void)hipFree(db);
+  (void)hipFree(dout);
+  return rc;
+}
+
+RBDI_API int rbdi_eval_rhs(rbdi_handle* h, int dirmask, double* D) {
+  if (!h || !D) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  h->ops->rhs(h, dirmask);
+  // D sits in state buffer 1; convert it through the staging buffer
+  std::swap(h->U[0], h->U[1]);
+  h->ops->state_to_f64(h, h->stage_buf);
+  std::swap(h->U[0], h->U[1]);
+  const size_t bytes = (size_t)h->P.ncell * h->nf * sizeof(double);
+  HIP_OK(hipMemcpyAsync(D, h->stage_buf, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
   return check_launch();
 }
 

@@ -49,6 +49,8 @@ struct StepArgs {
   double cfl;       // CFL number (device dt)
   double t_end;     // clip time (<= 0: none)
   double dt_fixed;  // > 0: use this dt instead of the CFL value
+  int rhs_only;     // bit 0: the final sweep stores D(U_in) itself; bits 1-3:
+                    // directions x, y, z left out of it (diagnostics)
 };
 
 // A step at or after t_end does no work.
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__
                                                 const T* __restrict__ Dacc, T* __restrict__ Uout,
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                                 StepArgs A, double bcoef, int stage) {
-  const double dt = sc->dtv[A.par];
+  const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -310,6 +312,10 @@ __global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__
   }
   T d[S::NF];
   sweep_core<S, T, 0>(P, W, pos, pc, tc, d);
+  if (A.rhs_only & 2) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) d[q] = T(0);
+  }
   const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
   double rate = 0.0;
   if (outlane) {
@@ -317,6 +323,11 @@ __global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__
     if (S::D > 1) {
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) d[q] = Dacc[q * P.fs + c] + d[q];
+    }
+    if (A.rhs_only) {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = d[q];
+      return;
     }
     const T dtt = (T)dt;
     const T b = (T)bcoef;
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restric
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) reduce_dt(sc, cflpart, A);
     if (step_done(sc, A)) return;  // uniform over the grid
   } else {
-    if (sc->dtv[A.par] == 0.0) return;  // uniform over the grid
+    if (!A.rhs_only && sc->dtv[A.par] == 0.0) return;  // uniform over the grid
   }
   const int x0 = blockIdx.x * TC;
   int seg, j, k;
@@ -429,6 +440,10 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restric
     ghost_fix<S, T, DIR>(P, mode, face, W);
     T d[S::NF];
     sweep_core<S, T, DIR>(P, W, pos, pc, tc, d);
+    if (A.rhs_only & (2 << DIR)) {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) d[q] = T(0);
+    }
     if (lane >= kHalo && lane < kHalo + kOut && pos < nd) {
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + lane] = d[q];
@@ -851,6 +866,61 @@ __global__ void k_r_from_sdf(Params P, const double* __restrict__ sdf, double in
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
   U[S::R * P.fs + c] = (T)(0.5 * (1.0 - tanh(sdf[c] * inv_w)));
+}
+
+// ---------------------------------------------------------------------------
+// Unit-level kernels (parity checks of single device functions)
+// ---------------------------------------------------------------------------
+
+// Face flux of (WL, WR) along DIR: out = {F[NT], u*, Vbar*_{DIR,0..2}}.
+template <class S, typename T, int DIR>
+__global__ void k_unit_flux(Params P, const double* __restrict__ WL, const double* __restrict__ WR,
+                            double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T L[S::NF], R[S::NF], F[S::NT], us, Vs[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) { L[q] = (T)WL[i * S::NF + q]; R[q] = (T)WR[i * S::NF + q]; }
+  hllc<S, DIR>(P, L, R, F, us, Vs);
+  double* o = out + (size_t)i * (S::NT + 4);
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) o[q] = (double)F[q];
+  o[S::NT] = (double)us;
+  for (int b = 0; b < 3; ++b) o[S::NT + 1 + b] = (double)Vs[b];
+}
+
+// Closure of conserved states: out = {W[NF], c2, sigma (9)}.
+template <class S, typename T>
+__global__ void k_unit_closure(Params P, const double* __restrict__ U, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T Uc[S::NF], W[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Uc[q] = (T)U[i * S::NF + q];
+  double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, J2 = 0.0;
+  cons_to_prim<S>(P, Uc, W, H, &J2);
+  double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
+  phases_w<S>(W, phi, rl);
+  mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
+  double* o = out + (size_t)i * (S::NF + 10);
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) o[q] = (double)W[q];
+  o[S::NF] = c2;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) o[S::NF + 1 + 3 * a + b] = (a == b ? -(double)W[S::wP] : 0.0) + 2.0 * G * H[3 * a + b];
+}
+
+// Per-stage solid sources of conserved states, in place.
+template <class S, typename T>
+__global__ void k_unit_sources(Params P, double* __restrict__ U, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T Uc[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Uc[q] = (T)U[i * S::NF + q];
+  if constexpr (S::S) solid_sources<S>(P, Uc);
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) U[i * S::NF + q] = (double)Uc[q];
 }
 
 }  // namespace rbdi

@@ -563,17 +563,20 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
   const double mL = L.rho * (SL - L.un), mR = R.rho * (SR - R.un);
   const double Ss = (R.P - L.P + L.un * mL - R.un * mR) * frcp(mL - mR);
   const int sp = P.solid_phase < 0 ? 0 : P.solid_phase;
-  if (P.riemann == RS_HLLC_LM && SL < 0.0 && SR > 0.0) {
+  // central form: HLLC-LM, and always for the elastoplastic system, whose
+  // star states do not satisfy the jump condition of the tangential traction
+  // across the contact (the central form has no jump at S* = 0)
+  if ((P.riemann == RS_HLLC_LM || S::S) && SL < 0.0 && SR > 0.0) {
     const double chiL = (SL - L.un) * frcp(SL - Ss), chiR = (SR - R.un) * frcp(SR - Ss);
     double cnL = 1, ctL = 1, cnR = 1, ctR = 1;
     if constexpr (S::S) {
       ctL = cbrt(chiL); cnL = 1.0 / (ctL * ctL);
       ctR = cbrt(chiR); cnR = 1.0 / (ctR * ctR);
     }
-    // acoustic scaling sin(min(1, Ma/Ma_lim) pi/2); 1 once either side
-    // reaches the limit
+    // acoustic scaling sin(min(1, Ma/Ma_lim) pi/2) of HLLC-LM; 1 once either
+    // side reaches the limit
     double ph = 1.0;
-    if (!(fabs(L.un) >= P.lm_mach * L.c || fabs(R.un) >= P.lm_mach * R.c)) {
+    if (P.riemann == RS_HLLC_LM && !(fabs(L.un) >= P.lm_mach * L.c || fabs(R.un) >= P.lm_mach * R.c)) {
       const double Ma = fmax(fabs(L.un) * frcp(L.c), fabs(R.un) * frcp(R.c));
       ph = sin(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
     }
@@ -587,11 +590,12 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
     }
     ustar = (T)(0.5 * (L.un + R.un) + 0.5 * (ph * SL * (chiL - 1.0) + aS * (chiL - chiR) + ph * SR * (chiR - 1.0)));
     if constexpr (S::S) {
-      const bool left = Ss >= 0.0;
+      // star states weighted by the contact's position in the fan
+      const double w = (Ss - SL) * frcp(SR - SL);
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const double v = left ? (double)WL[S::wV(DIR, b)] * cnL : (double)WR[S::wV(DIR, b)] * cnR;
-        Vstar[b] = (T)v;
+        const double vl = (double)WL[S::wV(DIR, b)] * cnL, vr = (double)WR[S::wV(DIR, b)] * cnR;
+        Vstar[b] = (T)(vr + w * (vl - vr));
       }
     }
     return;

@@ -360,3 +360,29 @@ def periodic_box(dim=2, n=32, nmat=1, seed=7, recon="bvd_thinc", riemann="hllc")
     return Problem(name="periodic", dim=dim, n=(n, shape[1], shape[0]), dx=(dx, dx, dx), origin=(0.0, 0.0, 0.0),
                    materials=mats, solid=False, bc=["periodic"] * 6, W0=W, recon=recon, riemann=riemann,
                    seed="none", cfl=0.4, t_end=1.0)
+
+
+def copper_piston_1d(n=400, v_p=30.0, length=10e-3, x_p=1e-3, eps=1e-6, t_end=1.2e-6, sigY=0.12e9):
+    """1D copper (Romenskii, rho0 8930, G0 46 GPa, perfect plasticity) driven
+    by a rigid piston (body x < x_p) moving at v_p; air as the second phase
+    with a negligible volume fraction."""
+    h = length / n
+    x = (np.arange(n) + 0.5) * h
+    cu = dict(TABLE1["copper"])
+    cu.update(rho0=8930.0, G0=46.0e9)
+    nf = 2 * 2 + 1 + 1 + 10
+    W = np.zeros((nf, 1, 1, n))
+    W[0] = 1.0 - eps     # phi_Cu
+    W[1] = cu["rho0"]
+    W[2] = 1.2
+    W[3] = 0.0
+    W[4] = 1.0e5
+    for a in range(3):
+        W[5 + 4 * a] = 1.0
+    W[14] = 0.0
+    sdf = (x - x_p).reshape(1, 1, n)
+    mats = [romenskii(cu["rho0"], cu["K0"], cu["G0"], cu["alpha"], cu["beta"], cu["Gamma0"], sigY), ideal(1.4)]
+    return Problem(name="copper_piston", dim=1, n=(n, 1, 1), dx=(h, 1.0, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=mats, solid=True, bc=["transmissive"] * 6, W0=W, sdf=sdf, width=1.0,
+                   v_r=(v_p, 0.0, 0.0), center=(x_p, 0.0, 0.0), recon="muscl", riemann="hllc", cfl=0.4,
+                   t_end=t_end)

@@ -59,7 +59,7 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
            "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
-           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times"]
+           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs"]
 NUM_KCLASS = 6
 KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt"]
 
@@ -97,6 +97,8 @@ def load():
     L.rbdi_last_error.restype = cp
     L.rbdi_set_kernel_timing.argtypes = [vp, ip]
     L.rbdi_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.rbdi_unit_eval.argtypes = [vp, ip, ip, dp, dp, dp, ip]
+    L.rbdi_eval_rhs.argtypes = [vp, ip, dp]
     _lib = L
     return L
 
@@ -267,6 +269,37 @@ class Solver:
         n = (ctypes.c_longlong * NUM_KCLASS)()
         _check(load().rbdi_kernel_times(self._h, _dp(ms), n))
         return {KCLASS[c]: (float(ms[c]), int(n[c])) for c in range(NUM_KCLASS)}
+
+    def eval_rhs(self, dirmask=7):
+        """D(U) of the current state, [nf, nz, ny, nx], over the directions of
+        dirmask (diagnostic)."""
+        out = np.empty(self.shape)
+        _check(load().rbdi_eval_rhs(self._h, int(dirmask), _dp(out)))
+        return out
+
+    def unit_flux(self, WL, WR, d):
+        """HLLC flux of faces (n x nf primitive left/right states) along d:
+        returns (F [n, nf-1], u* [n], Vbar* row [n, 3])."""
+        WL = _arr(WL).reshape(-1, self.nf)
+        WR = _arr(WR).reshape(-1, self.nf)
+        n = WL.shape[0]
+        out = np.zeros((n, self.nf + 3))
+        _check(load().rbdi_unit_eval(self._h, 0, int(d), _dp(WL), _dp(WR), _dp(out), n))
+        return out[:, : self.nf - 1], out[:, self.nf - 1], out[:, self.nf:]
+
+    def unit_closure(self, U):
+        """Closure of conserved states (n x nf): returns (W, c2, sigma [n,3,3])."""
+        U = _arr(U).reshape(-1, self.nf)
+        n = U.shape[0]
+        out = np.zeros((n, self.nf + 10))
+        _check(load().rbdi_unit_eval(self._h, 1, 0, _dp(U), _dp(U), _dp(out), n))
+        return out[:, : self.nf], out[:, self.nf], out[:, self.nf + 1:].reshape(n, 3, 3)
+
+    def unit_sources(self, U):
+        U = _arr(U).reshape(-1, self.nf)
+        out = np.zeros_like(U)
+        _check(load().rbdi_unit_eval(self._h, 2, 0, _dp(U), _dp(U), _dp(out), U.shape[0]))
+        return out
 
     def run(self, dts):
         for dt in dts:

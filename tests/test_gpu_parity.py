@@ -223,3 +223,48 @@ def test_3d_sphere_in_shock(rbdi):
     prob.seed = "original"
     orc, gpu, _ = _pair(rbdi, prob, nsteps=12)
     _check(orc, gpu, TOL64)
+
+
+# ---------------------------------------------------------------------------
+# Elastoplastic system
+# ---------------------------------------------------------------------------
+
+def test_copper_piston_1d_elastoplastic(rbdi):
+    """Copper driven by a rigid piston: Romenskii closure, Hencky strain,
+    solid HLLC, stretch-tensor non-conservative terms, plastic return."""
+    prob = inputs.copper_piston_1d(200)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=150)
+    _check(orc, gpu, TOL64)
+
+
+def test_copper_2d_oblique_piston(rbdi):
+    """2D copper/air with an oblique moving rigid wedge (shear and plastic flow
+    in the plane), 96 x 64, 40 steps."""
+    n = (96, 64)
+    prob1 = inputs.copper_piston_1d(8)
+    h = 10e-3 / n[0]
+    X, Y = np.meshgrid((np.arange(n[0]) + 0.5) * h, (np.arange(n[1]) + 0.5) * h)
+    W = np.zeros((17, 1, n[1], n[0]))
+    phi = 1e-6 + (1 - 2e-6) * 0.5 * (1 - np.tanh((Y - 4.5e-3) / h))
+    W[0] = phi
+    W[1] = 8930.0
+    W[2] = 1.2
+    W[5] = 1.0e5
+    for a in range(3):
+        W[6 + 4 * a] = 1.0
+    sdf = ((X - 2e-3) * np.cos(0.3) + (Y - 3e-3) * np.sin(0.3)).reshape(1, n[1], n[0])
+    prob = inputs.Problem(name="copper2d", dim=2, n=(n[0], n[1], 1), dx=(h, h, 1.0), origin=(0, 0, 0),
+                          materials=prob1.materials, solid=True,
+                          bc=["transmissive", "transmissive", "reflective", "transmissive", "transmissive",
+                              "transmissive"],
+                          W0=W, sdf=sdf, width=1.0, v_r=(40.0, 10.0, 0.0), center=(2e-3, 3e-3, 0.0),
+                          recon="bvd_thinc", riemann="hllc", cfl=0.3)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=40)
+    _check(orc, gpu, TOL64)
+
+
+def test_copper_indenter_3d_reduced(rbdi):
+    """The 3D copper indenter workload on 24^3 (8 steps)."""
+    prob = inputs.copper_indenter(24)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=8)
+    _check(orc, gpu, TOL64)

@@ -612,3 +612,51 @@ def test_force_summation_by_parts_and_linear_pressure():
         if kind == "linear":
             assert F[0] == pytest.approx(-0.7 * r.sum() * dx * dx, rel=1e-10)
             assert F[1] == pytest.approx(0.3 * r.sum() * dx * dx, rel=1e-10)
+
+
+def test_copper_piston_elastic_precursor_at_hugoniot_elastic_limit():
+    """1D copper (perfect plasticity, sigma_Y = 0.12 GPa) driven by a rigid
+    piston at 30 m/s: the elastic precursor carries -sigma_xx = HEL =
+    (K0 + 4 G0/3) sigma_Y / (2 G0) and runs at the longitudinal speed
+    sqrt((K0 + 4 G0/3)/rho0); behind the plastic wave the copper moves with
+    the piston; eps_p grows only behind the plastic wave."""
+    K, G, rho0, sY = 130.1e9, 46e9, 8930.0, 0.12e9
+    hel = (K + 4 * G / 3) * sY / (2 * G)
+    cl = math.sqrt((K + 4 * G / 3) / rho0)
+    p = inputs.copper_piston_1d(400)
+    o = oracle.Oracle(p)
+    o.run()
+    W = o.get_state_prim()[:, 0, 0]
+    x = (np.arange(400) + 0.5) * p.dx[0]
+    sxx = np.array([-o.thermo(W[:, i])["sigma"][0, 0] for i in range(400)])
+    u = W[3]
+    prec = (u > 3.0) & (u < 8.0)
+    assert prec.sum() >= 5
+    assert np.median(sxx[prec]) == pytest.approx(hel, rel=0.03)
+    front = x[np.nonzero(u > 1.0)[0].max()]
+    assert front == pytest.approx(1e-3 + cl * 1.2e-6, abs=4 * p.dx[0])
+    behind = (x > 1.5e-3) & (x < 4.5e-3)
+    assert np.all(np.abs(u[behind] - 30.0) < 0.1)
+    assert np.all(W[14][behind] > 1e-3) and np.all(np.abs(W[14][x > front]) < 1e-12)
+
+
+def test_indenter_keeps_mirror_symmetry():
+    """The 3D indenter is symmetric under x -> -x and y -> -y about the
+    cylinder axis; the elastoplastic step (with first-order fallbacks in
+    tension) must keep that symmetry to roundoff."""
+    import copy
+    p = inputs.copper_indenter(24)
+    p.W0 = p.W0.copy()
+    p.W0[5] = -100.0  # copper pulled away from the indenter: tension
+    p.v_r = (0.0, 0.0, 0.0)
+    o = oracle.Oracle(p)
+    for _ in range(2):
+        o.step(o.compute_dt(0.3))
+    U = o.get_state_cons()
+    names = p.cons_names()
+    for axis, odd in ((3, {"mx", "V01", "V10", "V02", "V20"}), (2, {"my", "V01", "V10", "V12", "V21"})):
+        for q, nm in enumerate(names):
+            m = np.flip(U[q], axis=axis - 1) * (-1.0 if nm in odd else 1.0)
+            scale = max(np.abs(U[q]).max(), 1e-300)
+            assert np.abs(U[q] - m).max() <= 1e-9 * scale + 1e-12, (axis, nm)
+    assert o.stats()["fallback"] > 0
