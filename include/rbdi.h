@@ -46,6 +46,7 @@ extern "C" {
 #define RBDI_API __attribute__((visibility("default")))
 
 typedef struct rbdi_handle rbdi_handle;
+typedef struct rbdi_batch rbdi_batch;
 
 typedef enum {
   RBDI_OK = 0,
@@ -230,6 +231,71 @@ RBDI_API int rbdi_unit_eval(rbdi_handle* h, int what, int dir, const double* a, 
  * set in dirmask (bit d = direction d; 7 = all). Diagnostic: overwrites the
  * handle's stage buffers; synchronises. */
 RBDI_API int rbdi_eval_rhs(rbdi_handle* h, int dirmask, double* D);
+
+/* ---------------------------------------------------------------------------
+ * Batched instances. A batch advances many independent instances (uneven
+ * grid sizes) together: every phase of a step (seeding, each direction sweep
+ * of each RK stage) is one launch over the merged tile list of all members,
+ * with a persistent grid and a tile shape chosen by rbdi_batch_autotune. The
+ * per-cell arithmetic is that of rbdi_step, so a member advanced in a batch
+ * is bitwise identical to the same instance advanced alone, for every tuning.
+ * (The paper runs one problem at a time; batching is this library's own
+ * throughput layer over the same step.)
+ * ------------------------------------------------------------------------- */
+
+/* Launch shape of the batched sweeps. */
+typedef struct {
+  int x_waves;    /* wavefronts per block of the final x sweep: 1, 2 or 4 */
+  int x_blocks;   /* persistent grid of the x sweep (blocks); 0: one block per tile */
+  int x_xcd;      /* 1: each of the 8 XCDs takes a contiguous run of x tiles */
+  int tile_cols;  /* x columns per y/z sweep tile: 4, 8, 16 or 32, with
+                     nfields * tile_cols * 65 values <= 64 KiB of LDS */
+  int t_blocks;   /* persistent grid of the y/z sweeps; 0: one block per tile */
+  int t_xcd;      /* 1: XCD-aware tile ranges for the y/z sweeps */
+  double x_us;    /* rbdi_batch_autotune output: mean duration of one x sweep
+                     launch over all members, microseconds */
+  double t_us;    /* the same for the y (and z) sweeps of one stage */
+} rbdi_tuning;
+
+/* Make a batch of count members (host array of handles). Members must share
+ * dim (2 or 3), nmat, solid and precision, have their state set, and carry
+ * no moving body (the rigid band of each member is built once, here). The
+ * batch does not own the members; they must outlive it. While a member
+ * belongs to a batch, rbdi_step, rbdi_advance, rbdi_set_state_*,
+ * rbdi_set_rigid_* and rbdi_set_stream on it return NOT_READY; reading it
+ * (get_state_*, status, rigid_force, conserved_totals) stays allowed. Every
+ * member is switched to the batch's stream (that of the first member).
+ * Allocates the batch's device tables. Errors: BAD_ARG, NOT_READY,
+ * UNSUPPORTED, OOM (a rigid band beyond the seeding capacity), HIP. */
+RBDI_API int rbdi_batch_create(int count, rbdi_handle* const* members, rbdi_batch** out);
+
+/* Release the batch (synchronises its stream); members become free again. */
+RBDI_API int rbdi_batch_destroy(rbdi_batch* b);
+
+/* Stream of the batch and of all its members (hipStream_t as void*). */
+RBDI_API int rbdi_batch_set_stream(rbdi_batch* b, void* hip_stream);
+
+/* Set / read the launch shape. set: BAD_ARG for values outside the ranges
+ * above; synchronises (the tile lists are rebuilt). */
+RBDI_API int rbdi_batch_set_tuning(rbdi_batch* b, const rbdi_tuning* t);
+RBDI_API int rbdi_batch_get_tuning(const rbdi_batch* b, rbdi_tuning* t);
+
+/* Time every candidate launch shape (reps launches each, HIP events, on the
+ * current states; the states are not changed: the timed launches evaluate
+ * the operator into the members' stage buffers), keep the fastest x and y/z
+ * shapes, and return them in *best (may be NULL). Synchronises. */
+RBDI_API int rbdi_batch_autotune(rbdi_batch* b, int reps, rbdi_tuning* best);
+
+/* Enqueue one step of every member. dts: NULL, or a host array of count
+ * values: dts[i] > 0 is member i's dt, dts[i] <= 0 takes member i's CFL dt
+ * (cfl > 0 required then). With dts the call synchronises the stream before
+ * uploading them; without, it does not synchronise. */
+RBDI_API int rbdi_batch_step(rbdi_batch* b, double cfl, const double* dts);
+
+/* Enqueue nsteps steps of every member, each with its own CFL dt computed on
+ * the device (as rbdi_advance, t_end per member clipping, <= 0: none). No
+ * host synchronisation. */
+RBDI_API int rbdi_batch_advance(rbdi_batch* b, double cfl, int nsteps, double t_end);
 
 /* Message of the last error on the calling thread ("" if none). */
 RBDI_API const char* rbdi_last_error(void);

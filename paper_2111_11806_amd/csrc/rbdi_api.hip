@@ -12,7 +12,7 @@
 #include <vector>
 
 #include "../../include/rbdi.h"
-#include "rbdi_kernels.hpp"
+#include "rbdi_batch.hpp"
 
 using namespace rbdi;
 
@@ -48,7 +48,6 @@ struct rbdi_handle {
   int par = 0;                  // parity of the next step
   bool cfl_valid = false;       // CFL partials of the current state are in cflpart
   double* cflpart = nullptr;    // CFL partials (one per block of their producer)
-  int npart = 0;                // number of valid partials
   int part_cap = 0;
   DevScalars* sc = nullptr;
   double* part = nullptr;       // reduction partials
@@ -60,6 +59,7 @@ struct rbdi_handle {
   bool dynamic_r = false;
   double t_host = 0.0;
   const Ops* ops = nullptr;
+  rbdi_batch* owner = nullptr;  // batch that steps this instance, if any
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;   // start/stop pairs
@@ -196,13 +196,11 @@ struct Impl {
       }
       sweep_x(h, Uin, U0, Uout, A, bc[s], s);
     }
-    h->npart = x_partials(h->P);
   }
   static void cfl(rbdi_handle* h) {
     Timed tm(h, 5);
     hipLaunchKernelGGL((k_cfl<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P, (const T*)u(h, 0),
-                       (const DevScalars*)h->sc, h->par, h->cflpart);
-    h->npart = kRedBlocks;
+                       h->sc, h->par, h->cflpart);
   }
   static void force(rbdi_handle* h, const double* c) {
     hipLaunchKernelGGL((k_force_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
@@ -216,7 +214,13 @@ struct Impl {
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, h->stream, (const double*)h->part, kRedBlocks,
                        2 * S::NF, h->red_out);
   }
-  static int part_blocks(const Params& P) { return std::max(x_partials(P), kRedBlocks); }
+  // capacity for the CFL partials of any x-sweep block size up to kMaxWPB
+  // wavefronts (a batch may choose another than the default)
+  static int part_blocks(const Params& P) {
+    const long long nseg = (P.n[0] + kOut - 1) / kOut;
+    const long long rows = (P.n[1] + kMaxWPB - 1) / kMaxWPB * kMaxWPB;
+    return (int)std::max<long long>(nseg * rows * P.n[2], kRedBlocks);
+  }
   // D(U^n) into U[1] (rigid mask from r), for diagnostics
   static void rhs(rbdi_handle* h, int dirmask) {
     StepArgs A{};
@@ -287,6 +291,12 @@ void free_all(rbdi_handle* h) {
 }
 
 }  // namespace
+
+// Members of a batch are stepped and configured by the batch only.
+static int free_member(const rbdi_handle* h) {
+  if (h->owner) return fail(RBDI_ERR_NOT_READY, "the instance belongs to a batch");
+  return RBDI_OK;
+}
 
 extern "C" {
 
@@ -399,12 +409,14 @@ RBDI_API int rbdi_nfields(const rbdi_handle* h) { return h ? h->nf : RBDI_ERR_BA
 
 RBDI_API int rbdi_set_stream(rbdi_handle* h, void* s) {
   if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   h->stream = static_cast<hipStream_t>(s);
   return RBDI_OK;
 }
 
 RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* e) {
   if (!h || !e) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (l < 0 || l >= h->desc.nmat) return fail(RBDI_ERR_BAD_ARG, "material index out of range");
   MatDev m{};
   m.kind = e->kind;
@@ -451,6 +463,7 @@ static int ready_materials(rbdi_handle* h) {
 
 RBDI_API int rbdi_set_bc_state(rbdi_handle* h, int face, const double* W) {
   if (!h || !W) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (face < 0 || face > 5) return fail(RBDI_ERR_BAD_ARG, "face must be 0..5");
   for (int q = 0; q < h->nf; ++q) {
     if (!std::isfinite(W[q])) return fail(RBDI_ERR_BAD_ARG, "non-finite boundary state");
@@ -468,6 +481,7 @@ static int stage_in(rbdi_handle* h, const double* src, int on_device) {
 
 RBDI_API int rbdi_set_state_prim(rbdi_handle* h, const double* W, int on_device) {
   if (!h || !W) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   int rc = ready_materials(h);
   if (rc) return rc;
   rc = stage_in(h, W, on_device);
@@ -482,6 +496,7 @@ RBDI_API int rbdi_set_state_prim(rbdi_handle* h, const double* W, int on_device)
 
 RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device) {
   if (!h || !U) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   int rc = ready_materials(h);
   if (rc) return rc;
   rc = stage_in(h, U, on_device);
@@ -519,6 +534,7 @@ RBDI_API int rbdi_get_state_cons(rbdi_handle* h, double* U, int on_device) {
 RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device, double width, const double v[3],
                                 const double omega[3], const double center[3]) {
   if (!h || !sdf || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (!(width > 0.0)) return fail(RBDI_ERR_BAD_ARG, "width must be > 0");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "set the state before the rigid field");
   const size_t bytes = (size_t)h->P.ncell * sizeof(double);
@@ -537,6 +553,7 @@ __global__ void k_set_motion_time(DevScalars* sc, int par) { sc->t_motion = sc->
 
 RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3], const double center[3]) {
   if (!h || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   bool moving = false;
   for (int a = 0; a < 3; ++a) {
     if (!std::isfinite(v[a]) || !std::isfinite(omega[a]) || !std::isfinite(center[a]))
@@ -560,7 +577,6 @@ static void enqueue_step(rbdi_handle* h, double dt_fixed, double cfl, double t_e
   if (dt_fixed <= 0.0 && !h->cfl_valid) h->ops->cfl(h);
   StepArgs A{};
   A.par = h->par;
-  A.npart = h->npart;
   A.cfl = cfl;
   A.t_end = t_end;
   A.dt_fixed = dt_fixed;
@@ -578,6 +594,7 @@ static void enqueue_step(rbdi_handle* h, double dt_fixed, double cfl, double t_e
 
 RBDI_API int rbdi_step(rbdi_handle* h, double dt) {
   if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBDI_ERR_BAD_ARG, "dt must be positive and finite");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
   enqueue_step(h, dt, 0.0, 0.0);
@@ -592,8 +609,8 @@ RBDI_API int rbdi_compute_dt(rbdi_handle* h, double cfl, double* dt) {
     h->ops->cfl(h);
     h->cfl_valid = true;
   }
-  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, h->stream, (const double*)h->cflpart, h->npart,
-                     h->red_out);
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, h->stream, (const double*)h->cflpart,
+                     (const DevScalars*)h->sc, h->red_out);
   double m = 0.0;
   HIP_OK(hipMemcpyAsync(&m, h->red_out, sizeof(m), hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
@@ -606,6 +623,7 @@ RBDI_API int rbdi_compute_dt(rbdi_handle* h, double cfl, double* dt) {
 
 RBDI_API int rbdi_advance(rbdi_handle* h, double cfl, int nsteps, double t_end) {
   if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (!(cfl > 0.0) || nsteps < 0) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 and nsteps >= 0");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
   for (int s = 0; s < nsteps; ++s) enqueue_step(h, 0.0, cfl, t_end);
@@ -709,6 +727,485 @@ RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out) {
   HIP_OK(hipMemcpyAsync(out, h->red_out, sizeof(double) * 2 * h->nf, hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   return check_launch();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched instances
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchOps;
+
+}  // namespace
+
+struct rbdi_batch {
+  std::vector<rbdi_handle*> m;
+  const BatchOps* ops = nullptr;
+  int dim = 0, nf = 0, elem = 8;
+  hipStream_t stream = nullptr;
+  void* inst = nullptr;          // BatchInst<T>[count] (device)
+  BatchItem* items = nullptr;    // seed | x | y | z item lists (device)
+  size_t item_cap = 0;
+  int n_seed = 0, n_x = 0, n_y = 0, n_z = 0;
+  int off_x = 0, off_y = 0, off_z = 0;
+  double* dtfix = nullptr;       // per-member fixed dt (device)
+  double* dtfix_host = nullptr;  // pinned staging of dtfix
+  int flip = 0;
+  rbdi_tuning tune{};
+};
+
+namespace {
+
+int lds_ok(const rbdi_batch* b, int tc) { return (size_t)b->nf * tc * kRS * b->elem <= 65536; }
+
+struct BatchOps {
+  void (*fill)(rbdi_batch*, const std::vector<int>& ntask, std::vector<unsigned char>&);
+  void (*seed)(rbdi_batch*, const BatchArgs&, int grid);
+  // which: 0 first sweep of the step (reduces dt), 1 first sweep of a later
+  // stage, 2 second sweep (3D: y after z, accumulating)
+  void (*tile)(rbdi_batch*, int dir, int which, const BatchArgs&, int grid, int tc);
+  void (*xsweep)(rbdi_batch*, const BatchArgs&, int grid, int wpb);
+};
+
+template <class S, typename T>
+struct BImpl {
+  static void fill(rbdi_batch* b, const std::vector<int>& ntask, std::vector<unsigned char>& out) {
+    out.assign(sizeof(BatchInst<T>) * b->m.size(), 0);
+    BatchInst<T>* t = reinterpret_cast<BatchInst<T>*>(out.data());
+    for (size_t i = 0; i < b->m.size(); ++i) {
+      rbdi_handle* h = b->m[i];
+      BatchInst<T> bi{};
+      bi.P = h->P;
+      for (int k = 0; k < 3; ++k) bi.U[k] = static_cast<T*>(h->U[k]);
+      bi.D = static_cast<T*>(h->D);
+      bi.sc = h->sc;
+      bi.cflpart = h->cflpart;
+      bi.tasks = h->tasks;
+      bi.ntask = ntask[i];
+      bi.par0 = h->par;
+      std::memcpy(&t[i], &bi, sizeof(bi));
+    }
+  }
+  static void seed(rbdi_batch* b, const BatchArgs& B, int grid) {
+    hipLaunchKernelGGL((kb_seed<S, T>), dim3(grid), dim3(256), 0, b->stream, (const BatchInst<T>*)b->inst,
+                       (const BatchItem*)b->items, B);
+  }
+  template <int DIR, int MODE, bool REDUCE>
+  static void tile_l(rbdi_batch* b, const BatchArgs& B, int grid, int tc, const BatchItem* items) {
+    const size_t lds = (size_t)S::NF * tc * kRS * sizeof(T);
+    hipLaunchKernelGGL((kb_sweep_tile<S, T, DIR, MODE, REDUCE>), dim3(grid), dim3(256), lds, b->stream,
+                       (const BatchInst<T>*)b->inst, items, B, tc);
+  }
+  static void tile(rbdi_batch* b, int dir, int which, const BatchArgs& B, int grid, int tc) {
+    const BatchItem* it = b->items + (dir == 1 ? b->off_y : b->off_z);
+    if constexpr (S::D == 3) {
+      if (dir == 2 && which == 0) tile_l<2, 0, true>(b, B, grid, tc, it);
+      else if (dir == 2) tile_l<2, 0, false>(b, B, grid, tc, it);
+      else tile_l<1, 1, false>(b, B, grid, tc, it);
+    } else {
+      if (which == 0) tile_l<1, 0, true>(b, B, grid, tc, it);
+      else tile_l<1, 0, false>(b, B, grid, tc, it);
+    }
+  }
+  static void xsweep(rbdi_batch* b, const BatchArgs& B, int grid, int wpb) {
+    hipLaunchKernelGGL((kb_sweep_x<S, T>), dim3(grid), dim3(kWave * wpb), 0, b->stream,
+                       (const BatchInst<T>*)b->inst, (const BatchItem*)(b->items + b->off_x), B);
+  }
+  static const BatchOps* ops() {
+    static const BatchOps o = {fill, seed, tile, xsweep};
+    return &o;
+  }
+};
+
+template <typename T>
+const BatchOps* pick_batch(int dim, int nmat, int solid) {
+  if (solid) return nullptr;
+  if (dim == 2 && nmat == 1) return BImpl<Sys<2, 1, false>, T>::ops();
+  if (dim == 2 && nmat == 2) return BImpl<Sys<2, 2, false>, T>::ops();
+  if (dim == 3 && nmat == 1) return BImpl<Sys<3, 1, false>, T>::ops();
+  if (dim == 3 && nmat == 2) return BImpl<Sys<3, 2, false>, T>::ops();
+  return nullptr;
+}
+
+// Tile lists of the current tuning, members in order of decreasing size (the
+// largest instances' tiles are taken first by a persistent grid).
+int batch_build_items(rbdi_batch* b, const std::vector<int>& ntask) {
+  std::vector<int> order(b->m.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->m[a]->P.ncell > b->m[c]->P.ncell; });
+  std::vector<BatchItem> seed, xs, ys, zs;
+  const int wpb = b->tune.x_waves, tc = b->tune.tile_cols;
+  for (int i : order) {
+    const Params& P = b->m[i]->P;
+    for (int t0 = 0; t0 < ntask[i]; t0 += 256) seed.push_back(BatchItem{i, t0, 0, 0, 0, {0, 0}});
+    const int gx = (P.n[0] + kOut - 1) / kOut, gy = (P.n[1] + wpb - 1) / wpb, gz = P.n[2];
+    for (int z = 0; z < gz; ++z)
+      for (int y = 0; y < gy; ++y)
+        for (int x = 0; x < gx; ++x)
+          xs.push_back(BatchItem{i, x, y, z, ((long long)z * gy + y) * gx + x, {0, 0}});
+    const int tx = (P.n[0] + tc - 1) / tc;
+    const int sy = (P.n[1] + kOut - 1) / kOut;
+    for (int z = 0; z < P.n[2]; ++z)
+      for (int y = 0; y < sy; ++y)
+        for (int x = 0; x < tx; ++x) ys.push_back(BatchItem{i, x, y, z, 0, {0, 0}});
+    if (b->dim == 3) {
+      const int sz = (P.n[2] + kOut - 1) / kOut;
+      for (int z = 0; z < sz; ++z)
+        for (int y = 0; y < P.n[1]; ++y)
+          for (int x = 0; x < tx; ++x) zs.push_back(BatchItem{i, x, y, z, 0, {0, 0}});
+    }
+  }
+  b->n_seed = (int)seed.size();
+  b->n_x = (int)xs.size();
+  b->n_y = (int)ys.size();
+  b->n_z = (int)zs.size();
+  b->off_x = b->n_seed;
+  b->off_y = b->off_x + b->n_x;
+  b->off_z = b->off_y + b->n_y;
+  const size_t total = (size_t)b->off_z + b->n_z;
+  std::vector<BatchItem> all;
+  all.reserve(total);
+  all.insert(all.end(), seed.begin(), seed.end());
+  all.insert(all.end(), xs.begin(), xs.end());
+  all.insert(all.end(), ys.begin(), ys.end());
+  all.insert(all.end(), zs.begin(), zs.end());
+  HIP_OK(hipStreamSynchronize(b->stream));
+  if (total > b->item_cap) {
+    if (b->items) (void)hipFree(b->items);
+    b->items = nullptr;
+    b->item_cap = 0;
+    HIP_OK(hipMalloc((void**)&b->items, total * sizeof(BatchItem)));
+    b->item_cap = total;
+  }
+  if (total) HIP_OK(hipMemcpy(b->items, all.data(), total * sizeof(BatchItem), hipMemcpyHostToDevice));
+  return RBDI_OK;
+}
+
+int batch_ntask(rbdi_batch* b, std::vector<int>& ntask) {
+  ntask.assign(b->m.size(), 0);
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    rbdi_handle* h = b->m[i];
+    if (h->P.seed == RBDI_SEED_NONE) continue;
+    DevScalars s{};
+    HIP_OK(hipMemcpy(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost));
+    if (s.band_count > h->task_cap) return fail(RBDI_ERR_OOM, "rigid band exceeds the seeding task capacity");
+    ntask[i] = s.band_count;
+  }
+  return RBDI_OK;
+}
+
+int batch_tables(rbdi_batch* b) {
+  std::vector<int> ntask;
+  int rc = batch_ntask(b, ntask);
+  if (rc) return rc;
+  std::vector<unsigned char> tab;
+  b->ops->fill(b, ntask, tab);
+  HIP_OK(hipStreamSynchronize(b->stream));
+  if (!b->inst) HIP_OK(hipMalloc(&b->inst, tab.size()));
+  HIP_OK(hipMemcpy(b->inst, tab.data(), tab.size(), hipMemcpyHostToDevice));
+  b->flip = 0;
+  return batch_build_items(b, ntask);
+}
+
+int check_tuning(const rbdi_batch* b, const rbdi_tuning& t) {
+  if (t.x_waves != 1 && t.x_waves != 2 && t.x_waves != 4) return fail(RBDI_ERR_BAD_ARG, "x_waves must be 1, 2 or 4");
+  if (t.tile_cols != 4 && t.tile_cols != 8 && t.tile_cols != 16 && t.tile_cols != 32)
+    return fail(RBDI_ERR_BAD_ARG, "tile_cols must be 4, 8, 16 or 32");
+  if (!lds_ok(b, t.tile_cols)) return fail(RBDI_ERR_BAD_ARG, "tile_cols exceeds 64 KiB of LDS for this system");
+  if (t.x_blocks < 0 || t.t_blocks < 0 || t.x_blocks > (1 << 20) || t.t_blocks > (1 << 20))
+    return fail(RBDI_ERR_BAD_ARG, "bad persistent grid size");
+  return RBDI_OK;
+}
+
+inline int grid_of(int blocks, int nitems) { return blocks > 0 ? std::min(blocks, nitems) : nitems; }
+
+void batch_enqueue_step(rbdi_batch* b, double cfl, double t_end, bool fixed) {
+  BatchArgs B{};
+  B.flip = b->flip;
+  B.cfl = cfl;
+  B.t_end = t_end;
+  B.dtfix = fixed ? b->dtfix : nullptr;
+  if (b->n_seed) {
+    B.nitems = b->n_seed;
+    B.xcd = 0;
+    b->ops->seed(b, B, b->n_seed);
+  }
+  const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
+  const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
+  for (int s = 0; s < 3; ++s) {
+    B.in = in_[s];
+    B.out = out_[s];
+    B.stage = s;
+    B.bcoef = bc[s];
+    B.xcd = b->tune.t_xcd;
+    if (b->dim == 3) {
+      B.nitems = b->n_z;
+      b->ops->tile(b, 2, s == 0 ? 0 : 1, B, grid_of(b->tune.t_blocks, b->n_z), b->tune.tile_cols);
+      B.nitems = b->n_y;
+      b->ops->tile(b, 1, 2, B, grid_of(b->tune.t_blocks, b->n_y), b->tune.tile_cols);
+    } else {
+      B.nitems = b->n_y;
+      b->ops->tile(b, 1, s == 0 ? 0 : 1, B, grid_of(b->tune.t_blocks, b->n_y), b->tune.tile_cols);
+    }
+    B.nitems = b->n_x;
+    B.xcd = b->tune.x_xcd;
+    b->ops->xsweep(b, B, grid_of(b->tune.x_blocks, b->n_x), b->tune.x_waves);
+  }
+  b->flip ^= 1;
+  for (rbdi_handle* h : b->m) {
+    h->par ^= 1;
+    h->cfl_valid = true;
+  }
+}
+
+void batch_free(rbdi_batch* b) {
+  if (b->inst) (void)hipFree(b->inst);
+  if (b->items) (void)hipFree(b->items);
+  if (b->dtfix) (void)hipFree(b->dtfix);
+  if (b->dtfix_host) (void)hipHostFree(b->dtfix_host);
+  b->inst = nullptr;
+  b->items = nullptr;
+  b->dtfix = nullptr;
+  b->dtfix_host = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+RBDI_API int rbdi_batch_create(int count, rbdi_handle* const* members, rbdi_batch** out) {
+  if (!members || !out || count < 1) return fail(RBDI_ERR_BAD_ARG, "need count >= 1 members and out");
+  *out = nullptr;
+  const rbdi_handle* h0 = members[0];
+  if (!h0) return fail(RBDI_ERR_BAD_ARG, "null member");
+  for (int i = 0; i < count; ++i) {
+    const rbdi_handle* h = members[i];
+    if (!h) return fail(RBDI_ERR_BAD_ARG, "null member");
+    for (int j = 0; j < i; ++j)
+      if (members[j] == h) return fail(RBDI_ERR_BAD_ARG, "a member appears twice");
+    if (h->desc.dim != h0->desc.dim || h->desc.nmat != h0->desc.nmat || h->desc.solid != h0->desc.solid ||
+        h->desc.precision != h0->desc.precision)
+      return fail(RBDI_ERR_BAD_ARG, "members must share dim, nmat, solid and precision");
+    if (h->owner) return fail(RBDI_ERR_NOT_READY, "a member already belongs to a batch");
+    if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "a member has no state");
+    if (h->dynamic_r) return fail(RBDI_ERR_UNSUPPORTED, "batched members must have static bodies");
+  }
+  const BatchOps* ops = h0->desc.precision == RBDI_FP64
+                            ? pick_batch<double>(h0->desc.dim, h0->desc.nmat, h0->desc.solid)
+                            : pick_batch<float>(h0->desc.dim, h0->desc.nmat, h0->desc.solid);
+  if (!ops) return fail(RBDI_ERR_UNSUPPORTED, "batches support 2D/3D fluid systems");
+  rbdi_batch* b = new rbdi_batch();
+  b->m.assign(members, members + count);
+  b->ops = ops;
+  b->dim = h0->desc.dim;
+  b->nf = h0->nf;
+  b->elem = h0->elem;
+  b->stream = h0->stream;
+  b->tune.x_waves = kWPB;
+  b->tune.tile_cols = b->elem == 8 ? 16 : 32;
+  while (!lds_ok(b, b->tune.tile_cols)) b->tune.tile_cols /= 2;
+  if (b->tune.tile_cols < 4) {
+    delete b;
+    return fail(RBDI_ERR_UNSUPPORTED, "system too wide for an LDS tile");
+  }
+  // members on the batch stream; static bands and CFL partials ready
+  for (rbdi_handle* h : b->m) {
+    h->stream = b->stream;
+    if (h->P.seed != RBDI_SEED_NONE && !h->band_valid) {
+      StepArgs A{};
+      A.par = h->par;
+      h->ops->band(h, A);
+      h->band_valid = true;
+    }
+    if (!h->cfl_valid) {
+      h->ops->cfl(h);
+      h->cfl_valid = true;
+    }
+  }
+  hipError_t e = hipMalloc((void**)&b->dtfix, sizeof(double) * count);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->dtfix_host, sizeof(double) * count);
+  if (e != hipSuccess) {
+    batch_free(b);
+    delete b;
+    return fail(RBDI_ERR_OOM, std::string("batch allocation: ") + hipGetErrorString(e));
+  }
+  int rc = check_launch();
+  if (!rc) rc = batch_tables(b);
+  if (rc) {
+    batch_free(b);
+    delete b;
+    return rc;
+  }
+  for (rbdi_handle* h : b->m) h->owner = b;
+  *out = b;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_batch_destroy(rbdi_batch* b) {
+  if (!b) return fail(RBDI_ERR_BAD_ARG, "null batch");
+  (void)hipStreamSynchronize(b->stream);
+  for (rbdi_handle* h : b->m) h->owner = nullptr;
+  batch_free(b);
+  delete b;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_batch_set_stream(rbdi_batch* b, void* s) {
+  if (!b) return fail(RBDI_ERR_BAD_ARG, "null batch");
+  b->stream = static_cast<hipStream_t>(s);
+  for (rbdi_handle* h : b->m) h->stream = b->stream;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_batch_set_tuning(rbdi_batch* b, const rbdi_tuning* t) {
+  if (!b || !t) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  int rc = check_tuning(b, *t);
+  if (rc) return rc;
+  const bool relist = t->x_waves != b->tune.x_waves || t->tile_cols != b->tune.tile_cols;
+  b->tune = *t;
+  if (!relist) return RBDI_OK;
+  std::vector<int> ntask;
+  rc = batch_ntask(b, ntask);
+  if (rc) return rc;
+  return batch_build_items(b, ntask);
+}
+
+RBDI_API int rbdi_batch_get_tuning(const rbdi_batch* b, rbdi_tuning* t) {
+  if (!b || !t) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  *t = b->tune;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_batch_step(rbdi_batch* b, double cfl, const double* dts) {
+  if (!b) return fail(RBDI_ERR_BAD_ARG, "null batch");
+  const int n = (int)b->m.size();
+  bool need_cfl = dts == nullptr;
+  if (dts)
+    for (int i = 0; i < n; ++i) {
+      if (!std::isfinite(dts[i])) return fail(RBDI_ERR_BAD_ARG, "non-finite dt");
+      need_cfl = need_cfl || !(dts[i] > 0.0);
+    }
+  if (need_cfl && !(cfl > 0.0)) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 for CFL steps");
+  if (dts) {
+    HIP_OK(hipStreamSynchronize(b->stream));  // the previous upload has been consumed
+    std::memcpy(b->dtfix_host, dts, sizeof(double) * n);
+    HIP_OK(hipMemcpyAsync(b->dtfix, b->dtfix_host, sizeof(double) * n, hipMemcpyHostToDevice, b->stream));
+  }
+  batch_enqueue_step(b, cfl, 0.0, dts != nullptr);
+  return check_launch();
+}
+
+RBDI_API int rbdi_batch_advance(rbdi_batch* b, double cfl, int nsteps, double t_end) {
+  if (!b) return fail(RBDI_ERR_BAD_ARG, "null batch");
+  if (!(cfl > 0.0) || nsteps < 0) return fail(RBDI_ERR_BAD_ARG, "cfl must be > 0 and nsteps >= 0");
+  for (int s = 0; s < nsteps; ++s) batch_enqueue_step(b, cfl, t_end, false);
+  return check_launch();
+}
+
+RBDI_API int rbdi_batch_autotune(rbdi_batch* b, int reps, rbdi_tuning* best) {
+  if (!b || reps < 1) return fail(RBDI_ERR_BAD_ARG, "null batch or reps < 1");
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  rbdi_tuning cur = b->tune;
+  // the operator of the current state: tile sweeps into D, x sweep into the
+  // stage buffer U[1]; nothing a step reads before writing it
+  BatchArgs B{};
+  B.flip = b->flip;
+  B.cfl = 1.0;
+  B.in = 0;
+  B.out = 1;
+  B.stage = 0;
+  B.bcoef = 1.0;
+  B.rhs_only = 1;
+  const int grids[4] = {0, 512, 1024, 2048};
+  auto time_it = [&](auto&& launch, double& us) -> int {
+    launch();
+    HIP_OK(hipEventRecord(e0, b->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    HIP_OK(hipEventRecord(e1, b->stream));
+    HIP_OK(hipEventSynchronize(e1));
+    int rc = check_launch();
+    if (rc) return rc;
+    float ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    us = 1e3 * ms / reps;
+    return RBDI_OK;
+  };
+  std::vector<int> ntask;
+  int rc = batch_ntask(b, ntask);
+  double best_t = 1e300, best_x = 1e300;
+  rbdi_tuning bt = cur;
+  // y/z sweeps: tile width x grid x XCD ranges
+  for (int tc : {4, 8, 16, 32}) {
+    if (rc || !lds_ok(b, tc)) continue;
+    b->tune.tile_cols = tc;
+    rc = batch_build_items(b, ntask);
+    for (int g : grids)
+      for (int xcd = 0; xcd < (g ? 2 : 1) && !rc; ++xcd) {
+        double us = 0.0;
+        rc = time_it(
+            [&]() {
+              B.xcd = xcd;
+              if (b->dim == 3) {
+                B.nitems = b->n_z;
+                b->ops->tile(b, 2, 1, B, grid_of(g, b->n_z), tc);
+                B.nitems = b->n_y;
+                b->ops->tile(b, 1, 2, B, grid_of(g, b->n_y), tc);
+              } else {
+                B.nitems = b->n_y;
+                b->ops->tile(b, 1, 1, B, grid_of(g, b->n_y), tc);
+              }
+            },
+            us);
+        if (!rc && us < best_t) {
+          best_t = us;
+          bt.tile_cols = tc;
+          bt.t_blocks = g;
+          bt.t_xcd = xcd;
+        }
+      }
+  }
+  for (int wpb : {1, 2, 4}) {
+    if (rc) break;
+    b->tune.x_waves = wpb;
+    rc = batch_build_items(b, ntask);
+    for (int g : grids)
+      for (int xcd = 0; xcd < (g ? 2 : 1) && !rc; ++xcd) {
+        double us = 0.0;
+        rc = time_it(
+            [&]() {
+              B.xcd = xcd;
+              B.nitems = b->n_x;
+              b->ops->xsweep(b, B, grid_of(g, b->n_x), wpb);
+            },
+            us);
+        if (!rc && us < best_x) {
+          best_x = us;
+          bt.x_waves = wpb;
+          bt.x_blocks = g;
+          bt.x_xcd = xcd;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    b->tune = cur;
+    (void)batch_build_items(b, ntask);
+    return rc;
+  }
+  bt.x_us = best_x;
+  bt.t_us = best_t;
+  b->tune = bt;
+  rc = batch_build_items(b, ntask);
+  if (rc) return rc;
+  if (best) *best = bt;
+  return RBDI_OK;
 }
 
 }  // extern "C"

@@ -22,7 +22,8 @@ namespace rbdi {
 constexpr int kWave = 64;
 constexpr int kOut = 58;       // cells updated per wavefront
 constexpr int kHalo = 3;
-constexpr int kWPB = 4;        // wavefronts per block in 2D/3D sweeps
+constexpr int kWPB = 4;        // wavefronts per block in 2D/3D x sweeps (default)
+constexpr int kMaxWPB = 4;     // largest x-sweep block (partial capacity)
 
 // Device-resident scalars of one instance. Per-step values live in two
 // slots indexed by the parity of the step: during step n (parity p) slot p
@@ -40,12 +41,12 @@ struct DevScalars {
   int nonphys;
   int band_count;     // seeding tasks of the current band
   int band_fail;      // band cells without a valid probe
+  int npart;          // CFL partials written by their last producer
 };
 
 // Host-side arguments of one step.
 struct StepArgs {
   int par;          // parity of the step
-  int npart;        // CFL partials to reduce (written by the previous step)
   double cfl;       // CFL number (device dt)
   double t_end;     // clip time (<= 0: none)
   double dt_fixed;  // > 0: use this dt instead of the CFL value
@@ -67,8 +68,10 @@ __device__ inline bool step_done(const DevScalars* sc, const StepArgs& a) {
 __device__ inline void reduce_dt(DevScalars* sc, const double* __restrict__ part, const StepArgs& a) {
   __shared__ double sh[16];
   double m = 0.0;
-  if (!(a.dt_fixed > 0.0))
-    for (int q = threadIdx.x; q < a.npart; q += blockDim.x) m = fmax(m, part[q]);
+  if (!(a.dt_fixed > 0.0)) {
+    const int np = sc->npart;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) m = fmax(m, part[q]);
+  }
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = m;
@@ -280,17 +283,18 @@ template <class S>
 constexpr int sweep_max_threads() { return 256; }
 
 template <class S, typename T>
-__global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
-                                                const T* __restrict__ Dacc, T* __restrict__ Uout,
-                                                DevScalars* __restrict__ sc, double* __restrict__ cflpart,
-                                                StepArgs A, double bcoef, int stage) {
+__device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restrict__ Uin, const T* __restrict__ U0,
+                                             const T* __restrict__ Dacc, T* __restrict__ Uout,
+                                             DevScalars* __restrict__ sc, double* __restrict__ cflpart,
+                                             const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
+                                             long long blin, int wpb, int nparts) {
   const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
-  const int seg = blockIdx.x, j = blockIdx.y * wpb + wave, k = blockIdx.z;
-  const size_t part_slot = (((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * wpb + wave;
+  const int seg = bx, j = by * wpb + wave, k = bz;
+  const size_t part_slot = (size_t)blin * wpb + wave;
+  if (stage == 2 && blin == 0 && threadIdx.x == 0) sc->npart = nparts;
   if (j >= P.n[1]) {  // whole wavefront beyond the grid
     if (stage == 2 && lane == 0) cflpart[part_slot] = 0.0;
     return;
@@ -370,6 +374,18 @@ __global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__
   }
 }
 
+template <class S, typename T>
+__global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
+                                                const T* __restrict__ Dacc, T* __restrict__ Uout,
+                                                DevScalars* __restrict__ sc, double* __restrict__ cflpart,
+                                                StepArgs A, double bcoef, int stage) {
+  const int wpb = blockDim.x / kWave;
+  const long long blin = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
+  sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
+                     blin, wpb, nparts);
+}
+
 // Sweeps along y and z (not final): a block stages a tile of kTC columns x
 // 64 positions along DIR of U_in in LDS with coalesced loads (rows of kTC
 // consecutive x), each wavefront then runs the sweep on one column at a time
@@ -386,21 +402,20 @@ constexpr int tile_cols() {
 }
 
 template <class S, typename T, int DIR, int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
-                                                   DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
-                                                   StepArgs A) {
-  constexpr int TC = tile_cols<S, T>();
-  __shared__ T tile[S::NF * TC * kRS];
+__device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+                                                DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
+                                                const StepArgs& A, int bx, int by, int bz, T* tile,
+                                                int TC) {
   if constexpr (REDUCE) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) reduce_dt(sc, cflpart, A);
+    if (bx == 0 && by == 0 && bz == 0) reduce_dt(sc, cflpart, A);
     if (step_done(sc, A)) return;  // uniform over the grid
   } else {
     if (!A.rhs_only && sc->dtv[A.par] == 0.0) return;  // uniform over the grid
   }
-  const int x0 = blockIdx.x * TC;
+  const int x0 = bx * TC;
   int seg, j, k;
-  if (DIR == 1) { seg = blockIdx.y; k = blockIdx.z; j = 0; }
-  else { j = blockIdx.y; seg = blockIdx.z; k = 0; }
+  if (DIR == 1) { seg = by; k = bz; j = 0; }
+  else { j = by; seg = bz; k = 0; }
   const int nd = P.n[DIR];
   const int base = seg * kOut - kHalo;
   for (int e = threadIdx.x; e < TC * kWave; e += blockDim.x) {
@@ -465,6 +480,16 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restric
       else Dacc[q * P.fs + cell] += v;
     }
   }
+}
+
+template <class S, typename T, int DIR, int MODE, bool REDUCE>
+__global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+                                                   DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
+                                                   StepArgs A) {
+  constexpr int TC = tile_cols<S, T>();
+  __shared__ T tile[S::NF * TC * kRS];
+  sweep_tile_body<S, T, DIR, MODE, REDUCE>(P, Uin, Dacc, sc, cflpart, A, blockIdx.x, blockIdx.y, blockIdx.z, tile,
+                                           TC);
 }
 
 // ---------------------------------------------------------------------------
@@ -588,6 +613,65 @@ __global__ void k_band_reset(DevScalars* sc, StepArgs A) {
 // rigid cell. Support cells are never rigid, so no thread reads a cell that
 // another one writes.
 template <class S, typename T>
+__device__ __forceinline__ void seed_one(const Params& P, T* __restrict__ U, const SeedTask& t, double tc) {
+  double Wc[1 << S::D][S::NF];
+#pragma unroll
+  for (int cb = 0; cb < (1 << S::D); ++cb) {
+    int cp[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < S::D; ++a) {
+      const int bit = (cb >> a) & 1;
+      cp[a] = t.lo[a] + ((bit && t.w[a] != 0.0) ? 1 : 0);
+    }
+    T Uc[S::NF], Wt[S::NF];
+    load_cons<S>(P, U, cell_index(P, cp[0], cp[1], cp[2]), Uc);
+    cons_to_prim<S>(P, Uc, Wt);
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Wc[cb][q] = (double)Wt[q];
+  }
+  int m = 1 << S::D;
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) {
+    m >>= 1;
+#pragma unroll
+    for (int cb = 0; cb < m; ++cb)
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q)
+        Wc[cb][q] = Wc[2 * cb][q] + t.w[a] * (Wc[2 * cb + 1][q] - Wc[2 * cb][q]);
+  }
+  int pi[3];
+  decode(P, t.c, pi[0], pi[1], pi[2]);
+  double xc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < S::D; ++a) xc[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xc[a] -= P.vr[a] * tc;
+  double v[3];
+  rigid_velocity(P, xc, v);
+  double Wm[S::NF], Wg[S::NF];
+  mirror<S>(Wc[0], t.n, v, Wm);
+  if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], t.n, Wg);
+  else {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) Wg[q] = Wm[q];
+  }
+  T Wt[S::NF], Ug[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) Wt[q] = (T)Wg[q];
+  Wt[S::R] = U[S::R * P.fs + t.c];
+  prim_to_cons<S>(P, Wt, Ug);
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) U[q * P.fs + t.c] = Ug[q];
+}
+
+// Sum of an int over the wavefront; lane 0 adds it to a counter (one atomic
+// per wavefront instead of one per lane).
+__device__ inline void wave_count_add(long long* counter, int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long*)counter, (unsigned long long)v);
+}
+
+template <class S, typename T>
 __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const SeedTask* __restrict__ tasks,
                                              int cap, DevScalars* __restrict__ sc, StepArgs A) {
   if (step_done(sc, A)) return;
@@ -595,58 +679,10 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
   const double tc = sc->t[A.par] - sc->t_motion;
   int nseed = 0;
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-    const SeedTask t = tasks[b];
-    double Wc[1 << S::D][S::NF];
-#pragma unroll
-    for (int cb = 0; cb < (1 << S::D); ++cb) {
-      int cp[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 0; a < S::D; ++a) {
-        const int bit = (cb >> a) & 1;
-        cp[a] = t.lo[a] + ((bit && t.w[a] != 0.0) ? 1 : 0);
-      }
-      T Uc[S::NF], Wt[S::NF];
-      load_cons<S>(P, U, cell_index(P, cp[0], cp[1], cp[2]), Uc);
-      cons_to_prim<S>(P, Uc, Wt);
-#pragma unroll
-      for (int q = 0; q < S::NF; ++q) Wc[cb][q] = (double)Wt[q];
-    }
-    int m = 1 << S::D;
-#pragma unroll
-    for (int a = 0; a < S::D; ++a) {
-      m >>= 1;
-#pragma unroll
-      for (int cb = 0; cb < m; ++cb)
-#pragma unroll
-        for (int q = 0; q < S::NF; ++q)
-          Wc[cb][q] = Wc[2 * cb][q] + t.w[a] * (Wc[2 * cb + 1][q] - Wc[2 * cb][q]);
-    }
-    int pi[3];
-    decode(P, t.c, pi[0], pi[1], pi[2]);
-    double xc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < S::D; ++a) xc[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xc[a] -= P.vr[a] * tc;
-    double v[3];
-    rigid_velocity(P, xc, v);
-    double Wm[S::NF], Wg[S::NF];
-    mirror<S>(Wc[0], t.n, v, Wm);
-    if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], t.n, Wg);
-    else {
-#pragma unroll
-      for (int q = 0; q < S::NF; ++q) Wg[q] = Wm[q];
-    }
-    T Wt[S::NF], Ug[S::NF];
-#pragma unroll
-    for (int q = 0; q < S::NF; ++q) Wt[q] = (T)Wg[q];
-    Wt[S::R] = U[S::R * P.fs + t.c];
-    prim_to_cons<S>(P, Wt, Ug);
-#pragma unroll
-    for (int q = 0; q < S::NT; ++q) U[q * P.fs + t.c] = Ug[q];
+    seed_one<S, T>(P, U, tasks[b], tc);
     ++nseed;
   }
-  if (nseed) atomicAdd((unsigned long long*)&sc->seeded, (unsigned long long)nseed);
+  wave_count_add(&sc->seeded, nseed);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +724,7 @@ __device__ inline double block_sum(double v, double* sh) {
 // not come from a step; the first sweep of the next step reduces them.
 template <class S, typename T>
 __global__ __launch_bounds__(kRedThreads) void k_cfl(Params P, const T* __restrict__ U,
-                                                    const DevScalars* __restrict__ sc, int par,
+                                                    DevScalars* __restrict__ sc, int par,
                                                     double* __restrict__ part) {
   __shared__ double sh[kRedThreads / 64];
   double m = 0.0;
@@ -707,11 +743,14 @@ __global__ __launch_bounds__(kRedThreads) void k_cfl(Params P, const T* __restri
   }
   m = -block_min(-m, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->npart = gridDim.x;
 }
 
-// Maximum of n partials (for rbdi_compute_dt).
-__global__ void k_max_partials(const double* __restrict__ part, int n, double* __restrict__ out) {
+// Maximum of the valid CFL partials (for rbdi_compute_dt).
+__global__ void k_max_partials(const double* __restrict__ part, const DevScalars* __restrict__ sc,
+                               double* __restrict__ out) {
   __shared__ double sh[4];
+  const int n = sc->npart;
   double m = 0.0;
   for (int q = threadIdx.x; q < n; q += blockDim.x) m = fmax(m, part[q]);
   m = -block_min(-m, sh);

@@ -47,6 +47,12 @@ class Eos(ctypes.Structure):
                 ("sigma_y", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("x_waves", ctypes.c_int), ("x_blocks", ctypes.c_int), ("x_xcd", ctypes.c_int),
+                ("tile_cols", ctypes.c_int), ("t_blocks", ctypes.c_int), ("t_xcd", ctypes.c_int),
+                ("x_us", ctypes.c_double), ("t_us", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
                 ("band_cells", ctypes.c_longlong), ("seeded", ctypes.c_longlong),
@@ -59,7 +65,9 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
            "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
-           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs"]
+           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
+           "rbdi_batch_create", "rbdi_batch_destroy", "rbdi_batch_set_stream", "rbdi_batch_set_tuning",
+           "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance"]
 NUM_KCLASS = 6
 KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt"]
 
@@ -99,6 +107,14 @@ def load():
     L.rbdi_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
     L.rbdi_unit_eval.argtypes = [vp, ip, ip, dp, dp, dp, ip]
     L.rbdi_eval_rhs.argtypes = [vp, ip, dp]
+    L.rbdi_batch_create.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.rbdi_batch_destroy.argtypes = [vp]
+    L.rbdi_batch_set_stream.argtypes = [vp, vp]
+    L.rbdi_batch_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.rbdi_batch_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.rbdi_batch_autotune.argtypes = [vp, ip, ctypes.POINTER(Tuning)]
+    L.rbdi_batch_step.argtypes = [vp, ctypes.c_double, dp]
+    L.rbdi_batch_advance.argtypes = [vp, ctypes.c_double, ip, ctypes.c_double]
     _lib = L
     return L
 
@@ -304,3 +320,67 @@ class Solver:
     def run(self, dts):
         for dt in dts:
             self.step(dt)
+
+
+def _tuning_dict(t):
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
+class Batch:
+    """Many :class:`Solver` instances advanced together (rbdi_batch_*). The
+    members stay readable through their own methods; stepping them on their
+    own is refused while the batch exists."""
+
+    def __init__(self, solvers, stream=None):
+        L = load()
+        self.members = list(solvers)
+        arr = (ctypes.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        b = ctypes.c_void_p()
+        _check(L.rbdi_batch_create(len(self.members), arr, ctypes.byref(b)))
+        self._b = b
+        if stream is not None:
+            self.set_stream(stream)
+
+    def close(self):
+        b = getattr(self, "_b", None)
+        if b:
+            load().rbdi_batch_destroy(b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(load().rbdi_batch_set_stream(self._b, ctypes.c_void_p(raw or 0)))
+
+    def tuning(self):
+        t = Tuning()
+        _check(load().rbdi_batch_get_tuning(self._b, ctypes.byref(t)))
+        return _tuning_dict(t)
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(load().rbdi_batch_get_tuning(self._b, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(load().rbdi_batch_set_tuning(self._b, ctypes.byref(t)))
+
+    def autotune(self, reps=5):
+        t = Tuning()
+        _check(load().rbdi_batch_autotune(self._b, int(reps), ctypes.byref(t)))
+        return _tuning_dict(t)
+
+    def step(self, dts=None, cfl=0.0):
+        """One step of every member: dts[i] > 0 fixed, <= 0 (or dts None) CFL."""
+        if dts is None:
+            _check(load().rbdi_batch_step(self._b, float(cfl), None))
+        else:
+            a = _arr(dts, len(self.members))
+            _check(load().rbdi_batch_step(self._b, float(cfl), _dp(a)))
+
+    def advance(self, cfl, nsteps, t_end=0.0):
+        _check(load().rbdi_batch_advance(self._b, float(cfl), int(nsteps), float(t_end)))
