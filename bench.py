@@ -26,6 +26,63 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_cylinder_1024x512_fp64.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_11806_amd", "csrc", f)
+                  for f in ("rbdi_api.hip", "rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_physics.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(ncell):
+    """HBM bytes of one RK stage (y sweep + x sweep, averages per launch) from
+    the rocprofv3 FETCH_SIZE / WRITE_SIZE summary, each counter scaled by what
+    it reads for a device copy of known size; None when the summary is
+    missing or was taken on other kernel sources, or on another grid."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha1") != kernel_source_hash() or int(kv["cells"]) != ncell:
+            return None
+        cb = float(kv["copy_bytes_read"])
+        f_scale = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+        w_scale = float(kv["copy_bytes_written"]) / (float(kv["copy_write_kib"]) * 1024.0)
+        fetch = (float(kv["sweep_y_fetch_kib"]) + float(kv["sweep_x_fetch_kib"])) * 1024.0 * f_scale
+        write = (float(kv["sweep_y_write_kib"]) + float(kv["sweep_x_write_kib"])) * 1024.0 * w_scale
+        return fetch + write
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def hbm_copy(nbytes=1 << 30, reps=20):
+    """Device-to-device copy of nbytes (torch), GB/s counting read + write."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del x, y
+    return {"bytes_per_launch": 2 * nbytes, "gbs": round(2 * nbytes * reps / (ms * 1e-3) / 1e9, 1)}
 
 
 def algorithmic_bytes_per_cell_step(n_dyn, n_static, elem):
@@ -57,7 +114,56 @@ def run_gpu(prob, precision, steps, warmup, cfl, timing_steps):
     s.advance(cfl, timing_steps, 0.0)
     kt = s.kernel_times()
     s.set_kernel_timing(False)
+    # kernel durations without per-launch event overhead: the sweeps of the
+    # middle stage of the last step, replayed back to back on its buffers
+    kt["replay_us"] = {"sweep_x": s.kernel_replay(0, 50), "sweep_y": s.kernel_replay(1, 50)}
     return s, ms, wall, st, kt
+
+
+def run_batched(steps, warmup, precision="fp32"):
+    """The 64-instance batch (seed 2111, sizes in {128..512}^2, 1-4 rigid
+    ellipses, Mach in [1.5, 3]): autotuned batched launches vs the same
+    instances advanced one after another with their own launches."""
+    import torch
+    from paper_2111_11806_amd import inputs, rbdi
+    probs = inputs.batch()
+    cells = sum(p.ncells for p in probs)
+    cfl = probs[0].cfl
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    sv = [rbdi.Solver(p, precision, stream=stream) for p in probs]
+    b = rbdi.Batch(sv)
+    tune = b.autotune(reps=3)
+    b.advance(cfl, warmup)
+    ms_b = timed(lambda: b.advance(cfl, steps))
+    bad = sum(s.status(raise_on_error=False)["nonphysical"] for s in sv)
+    b.close()
+    del sv
+    sq = [rbdi.Solver(p, precision, stream=stream) for p in probs]
+    for s in sq:
+        s.advance(cfl, warmup)
+
+    def seq():
+        for s in sq:
+            s.advance(cfl, steps)
+    ms_s = timed(seq)
+    del sq
+    return {"workload": "batch of 64 shock / rigid-ellipse instances, seed 2111", "instances": len(probs),
+            "cells": cells, "steps": steps, "dtype": "f32" if precision == "fp32" else "f64",
+            "value": cells * steps / (ms_b * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms_b / steps,
+            "sequential_value": cells * steps / (ms_s * 1e-3), "speedup_vs_sequential": ms_s / ms_b,
+            "nonphysical_members": int(bad),
+            "tuning": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()}}
 
 
 def main():
@@ -70,6 +176,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,13 +205,18 @@ def main():
     B64 = algorithmic_bytes_per_cell_step(n_dyn, n_static, 8)
     sx_ms, sx_n = kt64["sweep_x"]
     sy_ms, sy_n = kt64["sweep_y"]
-    stage_s = (sx_ms / max(sx_n, 1) + sy_ms / max(sy_n, 1)) * 1e-3
+    rx, ry = kt64["replay_us"]["sweep_x"], kt64["replay_us"]["sweep_y"]
+    stage_s = (rx + ry) * 1e-6
     achieved = (B64 / 3.0) * ncell / stage_s / 1e9
+    traffic = measured_traffic(ncell)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "algorithmic_bytes_per_stage": round(B64 / 3.0 * ncell),
             "kernel": "one RK stage: k_sweep<y> + k_sweep<x, final> (fp64)",
             "bytes_per_cell_step": B64,
-            "avg_us": {"sweep_x": round(sx_ms / max(sx_n, 1) * 1e3, 2),
+            "avg_us": {"sweep_x": round(rx, 2), "sweep_y": round(ry, 2)},
+            "avg_us_dispatch_events": {"sweep_x": round(sx_ms / max(sx_n, 1) * 1e3, 2),
                        "sweep_y": round(sy_ms / max(sy_n, 1) * 1e3, 2),
                        "seed": round(kt64["seed"][0] / max(kt64["seed"][1], 1) * 1e3, 2),
                        "cfl_dt": round(kt64["cfl_dt"][0] / max(kt64["cfl_dt"][1], 1) * 1e3, 2)}}
@@ -116,7 +229,8 @@ def main():
            "config": {"workload": "shock_cylinder", "nx": args.nx, "ny": args.ny, "cells": ncell,
                       "mach": 2.8, "cfl": cfl, "recon": prob.recon, "riemann": prob.riemann,
                       "t_reached": st64["t"]},
-           "roofline": roof}
+           "roofline": roof,
+           "hbm_copy": hbm_copy()}
 
     if not args.no_fp32:
         s32, ms32, wall32, st32, kt32 = run_gpu(prob, "fp32", args.steps, args.warmup, cfl, timing_steps)
@@ -135,8 +249,11 @@ def main():
         out["fp32"] = {"value": v32, "ms_per_step": ms32 / args.steps, "speedup_vs_fp64": v32 / value,
                        "rel_l1_vs_fp64_after_200_fixed_dt_steps": {n: float(x) for n, x in
                                                                    zip(prob.cons_names(), rel)},
-                       "avg_us": {"sweep_x": round(kt32["sweep_x"][0] / max(kt32["sweep_x"][1], 1) * 1e3, 2),
-                                  "sweep_y": round(kt32["sweep_y"][0] / max(kt32["sweep_y"][1], 1) * 1e3, 2)}}
+                       "avg_us": {"sweep_x": round(kt32["replay_us"]["sweep_x"], 2),
+                                  "sweep_y": round(kt32["replay_us"]["sweep_y"], 2)}}
+
+    if not args.no_batch:
+        out["batched"] = run_batched(args.batch_steps, 10)
 
     if not args.no_cpu_baseline:
         import oracle

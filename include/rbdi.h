@@ -202,8 +202,9 @@ RBDI_API int rbdi_rigid_force(rbdi_handle* h, const double center[3], double F[3
 RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
 
 /* Kernel timing (profiling aid). When enabled, every launch of the classes
- * below is bracketed by a HIP event pair on the handle's stream; the events
- * are kept until rbdi_kernel_times, which synchronises the stream, adds the
+ * below carries a HIP event pair attached to its dispatch
+ * (hipExtLaunchKernelGGL), so each pair measures that kernel's own duration
+ * on the handle's stream; the events are kept until rbdi_kernel_times, which synchronises the stream, adds the
  * elapsed times per class into ms[class] (milliseconds) and launches[class],
  * and releases the recorded pairs. Classes: 0 sweep along x (the last sweep,
  * with the RK combine), 1 sweep along y, 2 sweep along z, 3 seeding, 4 rigid
@@ -212,6 +213,14 @@ RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
 #define RBDI_NUM_KCLASS 6
 RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable);
 RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches);
+
+/* Mean duration of one sweep kernel, in microseconds: the sweep of class cls
+ * (0 x, 1 y, 2 z) of the middle RK stage of the last step is launched reps
+ * times back to back on that step's buffers between one HIP event pair
+ * (after one untimed launch). Its outputs are stage buffers that the next
+ * step rewrites before reading, so the state is unchanged. NOT_READY before
+ * the handle's first step or while it belongs to a batch. Synchronises. */
+RBDI_API int rbdi_kernel_replay(rbdi_handle* h, int cls, int reps, double* us);
 
 /* Unit-level evaluation of single device functions on n states (host
  * arrays, FP64, state-major: n x nfields), for parity checks of the

@@ -3,6 +3,7 @@
 // rbdi_kernels.hpp on the handle's stream. Instantiated for the systems
 // (dimension, materials, elastoplastic) and precisions the library supports.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdio>
@@ -60,6 +61,7 @@ struct rbdi_handle {
   double t_host = 0.0;
   const Ops* ops = nullptr;
   rbdi_batch* owner = nullptr;  // batch that steps this instance, if any
+  long long enqueued = 0;       // steps enqueued by this handle
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;   // start/stop pairs
@@ -69,28 +71,33 @@ struct rbdi_handle {
 
 namespace {
 
-// Brackets one launch with an event pair when kernel timing is enabled.
-struct Timed {
-  rbdi_handle* h;
-  size_t slot = (size_t)-1;
-  Timed(rbdi_handle* hh, int cls) : h(hh) {
-    if (!h->timing) return;
-    if (h->ev_used * 2 + 2 > h->ev.size()) {
-      for (int k = 0; k < 256; ++k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        h->ev.push_back(e);
-      }
+// Event pair for the next launch of class cls when kernel timing is on.
+bool timing_pair(rbdi_handle* h, int cls, hipEvent_t& e0, hipEvent_t& e1) {
+  if (!h->timing || cls < 0) return false;
+  if (h->ev_used * 2 + 2 > h->ev.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      h->ev.push_back(e);
     }
-    slot = h->ev_used++;
-    if (h->ev_cls.size() < h->ev_used) h->ev_cls.resize(h->ev_used);
-    h->ev_cls[slot] = cls;
-    (void)hipEventRecord(h->ev[2 * slot], h->stream);
   }
-  ~Timed() {
-    if (slot != (size_t)-1) (void)hipEventRecord(h->ev[2 * slot + 1], h->stream);
-  }
-};
+  const size_t slot = h->ev_used++;
+  if (h->ev_cls.size() < h->ev_used) h->ev_cls.resize(h->ev_used);
+  h->ev_cls[slot] = cls;
+  e0 = h->ev[2 * slot];
+  e1 = h->ev[2 * slot + 1];
+  return true;
+}
+
+// Launch on the handle's stream. With kernel timing on, the event pair is
+// part of the dispatch itself (hipExtLaunchKernelGGL), so the elapsed time is
+// the kernel's own duration.
+template <typename F, typename... Args>
+void launch(rbdi_handle* h, int cls, F kernel, dim3 g, dim3 b, unsigned shm, Args... args) {
+  hipEvent_t e0, e1;
+  if (timing_pair(h, cls, e0, e1)) hipExtLaunchKernelGGL(kernel, g, b, shm, h->stream, e0, e1, 0, args...);
+  else hipLaunchKernelGGL(kernel, g, b, shm, h->stream, args...);
+}
 
 }  // namespace
 
@@ -111,6 +118,7 @@ struct Ops {
   int (*part_blocks)(const Params&);
   void (*unit)(rbdi_handle*, int, int, const double*, const double*, double*, int);
   void (*rhs)(rbdi_handle*, int);
+  void (*replay)(rbdi_handle*, int);
 };
 
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -140,29 +148,26 @@ struct Impl {
                        sdf, inv_w, u(h, 0));
   }
   static void band(rbdi_handle* h, const StepArgs& A) {
-    Timed tm(h, 4);
     hipLaunchKernelGGL(k_band_reset, dim3(1), dim3(1), 0, h->stream, h->sc, A);
-    hipLaunchKernelGGL((k_band<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
-                       (const T*)u(h, 0), h->tasks, h->task_cap, h->sc, A);
+    launch(h, 4, k_band<S, T>, dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->P, (const T*)u(h, 0), h->tasks,
+           h->task_cap, h->sc, A);
   }
   static void seed(rbdi_handle* h, const StepArgs& A) {
-    Timed tm(h, 3);
-    hipLaunchKernelGGL((k_seed<S, T>), dim3(256), dim3(256), 0, h->stream, h->P, u(h, 0),
-                       (const SeedTask*)h->tasks, h->task_cap, h->sc, A);
+    launch(h, 3, k_seed<S, T>, dim3(256), dim3(256), 0, h->P, u(h, 0), (const SeedTask*)h->tasks, h->task_cap,
+           h->sc, A);
   }
   static int x_wpb() { return S::D == 1 ? 1 : kWPB; }
   static dim3 x_grid(const Params& P) {
     const unsigned nseg = (unsigned)((P.n[0] + kOut - 1) / kOut);
-    return dim3(nseg, (unsigned)((P.n[1] + x_wpb() - 1) / x_wpb()), (unsigned)P.n[2]);
+    return dim3((nseg + x_wpb() - 1) / x_wpb(), (unsigned)P.n[1], (unsigned)P.n[2]);
   }
   static int x_partials(const Params& P) {
     const dim3 g = x_grid(P);
     return (int)(g.x * g.y * g.z) * x_wpb();
   }
   static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
-    Timed tm(h, 0);
-    hipLaunchKernelGGL((k_sweep_x<S, T>), x_grid(h->P), dim3(kWave * x_wpb()), 0, h->stream, h->P, Uin, U0,
-                       (const T*)h->D, Uout, h->sc, h->cflpart, A, b, stage);
+    launch(h, 0, k_sweep_x<S, T>, x_grid(h->P), dim3(kWave * x_wpb()), 0, h->P, Uin, U0, (const T*)h->D, Uout, h->sc,
+           h->cflpart, A, b, stage);
   }
   template <int DIR, int MODE, bool REDUCE>
   static void sweep_t(rbdi_handle* h, const T* Uin, const StepArgs& A) {
@@ -171,17 +176,13 @@ struct Impl {
     const unsigned nseg = (unsigned)((P.n[DIR] + kOut - 1) / kOut);
     const unsigned gx = (unsigned)((P.n[0] + TC - 1) / TC);
     const dim3 grid = DIR == 1 ? dim3(gx, nseg, (unsigned)P.n[2]) : dim3(gx, (unsigned)P.n[1], nseg);
-    Timed tm(h, DIR);
-    hipLaunchKernelGGL((k_sweep_tile<S, T, DIR, MODE, REDUCE>), grid, dim3(256), 0, h->stream, P, Uin,
-                       static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
+    launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE>, grid, dim3(256), 0, P, Uin, static_cast<T*>(h->D), h->sc,
+           (const double*)h->cflpart, A);
   }
   static void stages(rbdi_handle* h, const StepArgs& A) {
     const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
     const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
-    if constexpr (S::D == 1) {
-      Timed tm(h, 5);
-      hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(256), 0, h->stream, h->sc, (const double*)h->cflpart, A);
-    }
+    if constexpr (S::D == 1) launch(h, 5, k_reduce_dt, dim3(1), dim3(256), 0, h->sc, (const double*)h->cflpart, A);
     for (int s = 0; s < 3; ++s) {
       const T* Uin = u(h, in_[s]);
       const T* U0 = u(h, 0);
@@ -198,9 +199,8 @@ struct Impl {
     }
   }
   static void cfl(rbdi_handle* h) {
-    Timed tm(h, 5);
-    hipLaunchKernelGGL((k_cfl<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P, (const T*)u(h, 0),
-                       h->sc, h->par, h->cflpart);
+    launch(h, 5, k_cfl<S, T>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->P, (const T*)u(h, 0), h->sc, h->par,
+           h->cflpart);
   }
   static void force(rbdi_handle* h, const double* c) {
     hipLaunchKernelGGL((k_force_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
@@ -218,8 +218,8 @@ struct Impl {
   // wavefronts (a batch may choose another than the default)
   static int part_blocks(const Params& P) {
     const long long nseg = (P.n[0] + kOut - 1) / kOut;
-    const long long rows = (P.n[1] + kMaxWPB - 1) / kMaxWPB * kMaxWPB;
-    return (int)std::max<long long>(nseg * rows * P.n[2], kRedBlocks);
+    const long long segs = (nseg + kMaxWPB - 1) / kMaxWPB * kMaxWPB;
+    return (int)std::max<long long>(segs * P.n[1] * P.n[2], kRedBlocks);
   }
   // D(U^n) into U[1] (rigid mask from r), for diagnostics
   static void rhs(rbdi_handle* h, int dirmask) {
@@ -234,6 +234,22 @@ struct Impl {
       sweep_t<1, 0, false>(h, U0, A);
     }
     sweep_x(h, U0, U0, u(h, 1), A, 1.0, 0);
+  }
+  // One launch of a sweep of the middle RK stage of the last step, on that
+  // step's buffers (inputs U(1), U^n, D; outputs D or U(2), which the next
+  // step rewrites before reading): cls 0 x sweep, 1 y sweep, 2 z sweep.
+  static void replay(rbdi_handle* h, int cls) {
+    StepArgs A{};
+    A.par = h->par ^ 1;
+    const T* U1 = u(h, 1);
+    if (cls == 0) sweep_x(h, U1, u(h, 0), u(h, 2), A, 0.25, 1);
+    if constexpr (S::D >= 2)
+      if (cls == 1) {
+        if constexpr (S::D == 3) sweep_t<1, 1, false>(h, U1, A);
+        else sweep_t<1, 0, false>(h, U1, A);
+      }
+    if constexpr (S::D == 3)
+      if (cls == 2) sweep_t<2, 0, false>(h, U1, A);
   }
   // what: 0 face flux (dir), 1 closure, 2 solid sources
   static void unit(rbdi_handle* h, int what, int dir, const double* a, const double* b, double* out, int n) {
@@ -250,7 +266,7 @@ struct Impl {
   }
   static const Ops* ops() {
     static const Ops o = {prim_to_state, state_to_prim, state_to_f64, f64_to_state, r_from_sdf, band, seed,
-                          stages, cfl, force, totals, part_blocks, unit, rhs};
+                          stages, cfl, force, totals, part_blocks, unit, rhs, replay};
     return &o;
   }
 };
@@ -590,6 +606,7 @@ static void enqueue_step(rbdi_handle* h, double dt_fixed, double cfl, double t_e
   h->ops->stages(h, A);
   h->par ^= 1;
   h->cfl_valid = true;
+  h->enqueued += 1;
 }
 
 RBDI_API int rbdi_step(rbdi_handle* h, double dt) {
@@ -687,6 +704,29 @@ RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches) 
   }
   h->ev_used = 0;
   return RBDI_OK;
+}
+
+RBDI_API int rbdi_kernel_replay(rbdi_handle* h, int cls, int reps, double* us) {
+  if (!h || !us || reps < 1 || cls < 0 || cls > 2) return fail(RBDI_ERR_BAD_ARG, "bad kernel_replay argument");
+  if (cls >= h->desc.dim) return fail(RBDI_ERR_BAD_ARG, "no sweep along that direction");
+  if (h->owner || h->enqueued < 1) return fail(RBDI_ERR_NOT_READY, "replay needs a step of this handle first");
+  const bool was = h->timing;
+  h->timing = false;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  h->ops->replay(h, cls);
+  HIP_OK(hipEventRecord(e0, h->stream));
+  for (int r = 0; r < reps; ++r) h->ops->replay(h, cls);
+  HIP_OK(hipEventRecord(e1, h->stream));
+  HIP_OK(hipEventSynchronize(e1));
+  h->timing = was;
+  float ms = 0.0f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1e3 * ms / reps;
+  return check_launch();
 }
 
 RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st) {
@@ -842,7 +882,7 @@ int batch_build_items(rbdi_batch* b, const std::vector<int>& ntask) {
   for (int i : order) {
     const Params& P = b->m[i]->P;
     for (int t0 = 0; t0 < ntask[i]; t0 += 256) seed.push_back(BatchItem{i, t0, 0, 0, 0, {0, 0}});
-    const int gx = (P.n[0] + kOut - 1) / kOut, gy = (P.n[1] + wpb - 1) / wpb, gz = P.n[2];
+    const int gx = ((P.n[0] + kOut - 1) / kOut + wpb - 1) / wpb, gy = P.n[1], gz = P.n[2];
     for (int z = 0; z < gz; ++z)
       for (int y = 0; y < gy; ++y)
         for (int x = 0; x < gx; ++x)

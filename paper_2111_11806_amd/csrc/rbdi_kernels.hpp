@@ -292,10 +292,12 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   if (dt == 0.0) return;  // uniform over the grid
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int seg = bx, j = by * wpb + wave, k = bz;
+  // the wavefronts of a block take consecutive segments of one row, so the
+  // cache lines shared by neighbouring segments are fetched once
+  const int seg = bx * wpb + wave, j = by, k = bz;
   const size_t part_slot = (size_t)blin * wpb + wave;
   if (stage == 2 && blin == 0 && threadIdx.x == 0) sc->npart = nparts;
-  if (j >= P.n[1]) {  // whole wavefront beyond the grid
+  if (seg * kOut >= P.n[0]) {  // whole wavefront beyond the row
     if (stage == 2 && lane == 0) cflpart[part_slot] = 0.0;
     return;
   }

@@ -65,7 +65,7 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
            "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
-           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
+           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs", "rbdi_kernel_replay",
            "rbdi_batch_create", "rbdi_batch_destroy", "rbdi_batch_set_stream", "rbdi_batch_set_tuning",
            "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance"]
 NUM_KCLASS = 6
@@ -107,6 +107,7 @@ def load():
     L.rbdi_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
     L.rbdi_unit_eval.argtypes = [vp, ip, ip, dp, dp, dp, ip]
     L.rbdi_eval_rhs.argtypes = [vp, ip, dp]
+    L.rbdi_kernel_replay.argtypes = [vp, ip, ip, dp]
     L.rbdi_batch_create.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.rbdi_batch_destroy.argtypes = [vp]
     L.rbdi_batch_set_stream.argtypes = [vp, vp]
@@ -285,6 +286,13 @@ class Solver:
         n = (ctypes.c_longlong * NUM_KCLASS)()
         _check(load().rbdi_kernel_times(self._h, _dp(ms), n))
         return {KCLASS[c]: (float(ms[c]), int(n[c])) for c in range(NUM_KCLASS)}
+
+    def kernel_replay(self, cls, reps=20):
+        """Mean duration (us) of the x (0), y (1) or z (2) sweep of the middle
+        RK stage, launched reps times back to back on the last step's buffers."""
+        out = ctypes.c_double()
+        _check(load().rbdi_kernel_replay(self._h, int(cls), int(reps), ctypes.byref(out)))
+        return out.value
 
     def eval_rhs(self, dirmask=7):
         """D(U) of the current state, [nf, nz, ny, nx], over the directions of
