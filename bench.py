@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_cylinder_1024x512_fp64.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_11806_amd", "csrc", f)
-                  for f in ("rbdi_api.hip", "rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_physics.hpp")]
+                  for f in ("rbdi_api.hip", "rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_mlp.hpp", "rbdi_physics.hpp")]
 
 
 def kernel_source_hash():

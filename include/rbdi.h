@@ -47,6 +47,7 @@ extern "C" {
 
 typedef struct rbdi_handle rbdi_handle;
 typedef struct rbdi_batch rbdi_batch;
+typedef struct rbdi_mlp rbdi_mlp;
 
 typedef enum {
   RBDI_OK = 0,
@@ -116,6 +117,8 @@ typedef struct {
   long long probe_fail;   /* of band_cells, those without a valid probe (last band build) */
   int nonphysical;        /* 1 once a non-admissible updated cell was found */
   long long first_bad;    /* linear interior index of the first such cell, or -1 */
+  long long surr_net;     /* plastic-return evaluations closed by the surrogate (cumulative) */
+  long long surr_exact;   /* ... closed by the exact closure: outside the envelope or flagged */
 } rbdi_stats;
 
 /* Create an instance on the current HIP device. Allocates every device buffer
@@ -208,9 +211,9 @@ RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
  * elapsed times per class into ms[class] (milliseconds) and launches[class],
  * and releases the recorded pairs. Classes: 0 sweep along x (the last sweep,
  * with the RK combine), 1 sweep along y, 2 sweep along z, 3 seeding, 4 rigid
- * band compaction, 5 CFL reduction. ms and launches hold RBDI_NUM_KCLASS
- * entries each. */
-#define RBDI_NUM_KCLASS 6
+ * band compaction, 5 CFL reduction, 6 surrogate source pass. ms and launches
+ * hold RBDI_NUM_KCLASS entries each. */
+#define RBDI_NUM_KCLASS 7
 RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable);
 RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches);
 
@@ -305,6 +308,60 @@ RBDI_API int rbdi_batch_step(rbdi_batch* b, double cfl, const double* dts);
  * the device (as rbdi_advance, t_end per member clipping, <= 0: none). No
  * host synchronisation. */
 RBDI_API int rbdi_batch_advance(rbdi_batch* b, double cfl, int nsteps, double t_end);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate closure (not in the paper: a learned replacement of the per-cell
+ * elastoplastic closure). A 6 -> 64 -> 64 -> 64 -> 6 ReLU network with BF16
+ * weights and FP32 accumulation, evaluated and trained by matrix-core
+ * kernels of this library. For b = Vbar Vbar^T and X = b - I it returns the
+ * higher-order remainders of the coefficients of H = (1/2) ln b =
+ * a0 I + a1 X + a2 X^2 and of H^2 (Cayley-Hamilton form; the Hencky strain
+ * of Sec. 2.1.2) beyond their series to order X^3, from six invariant
+ * features of X. With a network set on a solid handle (rbdi_set_surrogate)
+ * the per-stage elastoplastic sources (det(Vbar) renormalisation and the
+ * perfect-plasticity radial return) run in a separate pass that takes H and
+ * J2 = H:H from the network; outside the envelope |X|_F <= tau_max, or when
+ * the network's J2 disagrees with the one its H implies by more than 1e-6
+ * relative (the error flag), that cell uses the exact closure.
+ * Parameter vector: FP32, 9158 values, row-major [out][in] per layer:
+ * W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[6][64] b4[6].
+ * Features z and targets t: n x 6 FP32, sample-major. All calls below run
+ * on the null stream and synchronise; they allocate temporary device memory.
+ * ------------------------------------------------------------------------- */
+
+/* Create a network (all parameters zero) on the current device. */
+RBDI_API int rbdi_mlp_create(rbdi_mlp** out);
+RBDI_API int rbdi_mlp_destroy(rbdi_mlp* m);
+
+/* Set the FP32 parameters (host, 9158 values; BF16 device copies are made)
+ * and the envelope / input scale tau_max in (0, 1); resets the optimiser. */
+RBDI_API int rbdi_mlp_set_params(rbdi_mlp* m, const float* params, double tau_max);
+RBDI_API int rbdi_mlp_get_params(rbdi_mlp* m, float* params, double* tau_max);
+
+/* Features and exact targets (normalised remainders) of n stretch tensors
+ * V (host, n x 9, FP64, row-major 3x3 each) for the scale tau_max. */
+RBDI_API int rbdi_mlp_data(const double* V, int n, double tau_max, float* z, float* t);
+
+/* Network outputs y (host, n x 6) for features z (host, n x 6). */
+RBDI_API int rbdi_mlp_forward(rbdi_mlp* m, const float* z, int n, float* y);
+
+/* Gradient (host, 9158 values, flat layout) and value of the mean squared
+ * error over the n samples and 6 outputs, by the device forward and
+ * backward passes (BF16 operands, FP32 accumulation). */
+RBDI_API int rbdi_mlp_grad(rbdi_mlp* m, const float* z, const float* t, int n, float* grad, float* loss);
+
+/* iters Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr with a
+ * cosine decay to zero) on consecutive batches of `batch` samples (a
+ * multiple of 64), cycling through the n samples in their given order
+ * (shuffle them first). losses (host, iters values, may be NULL) receives
+ * each batch's loss before its update. */
+RBDI_API int rbdi_mlp_train(rbdi_mlp* m, const float* z, const float* t, int n, int batch, int iters, float lr,
+                            float* losses);
+
+/* Use network m for the elastoplastic sources of handle h (solid systems
+ * only), or the exact closure again when m is NULL. The network must outlive
+ * its use by h. */
+RBDI_API int rbdi_set_surrogate(rbdi_handle* h, rbdi_mlp* m);
 
 /* Message of the last error on the calling thread ("" if none). */
 RBDI_API const char* rbdi_last_error(void);

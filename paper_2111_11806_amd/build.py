@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "librbdi.so")
 SOURCES = ["rbdi_api.hip"]
-HEADERS = ["rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_physics.hpp"]
+HEADERS = ["rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_mlp.hpp", "rbdi_physics.hpp"]
 ARCH = os.environ.get("RBDI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -14,6 +14,7 @@
 
 #include "../../include/rbdi.h"
 #include "rbdi_batch.hpp"
+#include "rbdi_mlp.hpp"
 
 using namespace rbdi;
 
@@ -61,6 +62,7 @@ struct rbdi_handle {
   double t_host = 0.0;
   const Ops* ops = nullptr;
   rbdi_batch* owner = nullptr;  // batch that steps this instance, if any
+  rbdi_mlp* mlp = nullptr;      // surrogate closure of the elastoplastic sources, if set
   long long enqueued = 0;       // steps enqueued by this handle
   // kernel timing
   bool timing = false;
@@ -101,7 +103,36 @@ void launch(rbdi_handle* h, int cls, F kernel, dim3 g, dim3 b, unsigned shm, Arg
 
 }  // namespace
 
+struct rbdi_mlp {
+  __bf16* blob = nullptr;   // padded BF16 operands (see MlpDev)
+  float* bias = nullptr;    // kBiasN
+  float* master = nullptr;  // FP32 parameters, flat layout
+  float* m1 = nullptr;      // Adam moments
+  float* m2 = nullptr;
+  float* sum = nullptr;     // kNParam + 1 (gradient + loss)
+  double tau_max = 1.0;
+  int step = 0;
+};
+
 namespace {
+
+MlpDev mlp_dev(const rbdi_mlp* m) {
+  MlpDev d;
+  const __bf16* b = m->blob;
+  d.W1 = b;
+  d.W2 = b + kW1n;
+  d.W3 = d.W2 + kW2n;
+  d.W4 = d.W3 + kW3n;
+  d.W2T = d.W4 + kW4n;
+  d.W3T = d.W2T + kW2Tn;
+  d.W4T = d.W3T + kW3Tn;
+  d.b1 = m->bias;
+  d.b2 = m->bias + 64;
+  d.b3 = m->bias + 128;
+  d.b4 = m->bias + 192;
+  d.tau_max = m->tau_max;
+  return d;
+}
 
 struct Ops {
   void (*prim_to_state)(rbdi_handle*, const double*);
@@ -179,9 +210,17 @@ struct Impl {
     launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE>, grid, dim3(256), 0, P, Uin, static_cast<T*>(h->D), h->sc,
            (const double*)h->cflpart, A);
   }
+  static void sources_mlp(rbdi_handle* h, T* Uout, const StepArgs& A, int stage) {
+    if constexpr (S::S)
+      launch(h, 6, k_sources_mlp<S, T>, dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->P, Uout,
+             (const T*)u(h, 0), mlp_dev(h->mlp), h->sc, h->cflpart, A, stage);
+  }
   static void stages(rbdi_handle* h, const StepArgs& A) {
     const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
-    const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
+    // with the surrogate pass the last stage writes U(1)'s buffer (U^n stays
+    // intact for the pass's rigid mask) and the buffers swap afterwards
+    const bool surr = h->P.surr != 0;
+    const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, surr ? 1 : 0};
     if constexpr (S::D == 1) launch(h, 5, k_reduce_dt, dim3(1), dim3(256), 0, h->sc, (const double*)h->cflpart, A);
     for (int s = 0; s < 3; ++s) {
       const T* Uin = u(h, in_[s]);
@@ -196,7 +235,9 @@ struct Impl {
         else sweep_t<1, 0, false>(h, Uin, A);
       }
       sweep_x(h, Uin, U0, Uout, A, bc[s], s);
+      if (surr) sources_mlp(h, Uout, A, s);
     }
+    if (surr) std::swap(h->U[0], h->U[1]);
   }
   static void cfl(rbdi_handle* h) {
     launch(h, 5, k_cfl<S, T>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->P, (const T*)u(h, 0), h->sc, h->par,
@@ -300,6 +341,7 @@ void free_all(rbdi_handle* h) {
   for (auto& p : h->U)
     if (p) { (void)hipFree(p); p = nullptr; }
   void* ptrs[] = {h->D, h->stage_buf, h->tasks, h->sc, h->part, h->red_out, h->cflpart};
+  h->mlp = nullptr;
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   h->D = nullptr; h->stage_buf = nullptr; h->tasks = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
@@ -742,6 +784,8 @@ RBDI_API int rbdi_status(rbdi_handle* h, rbdi_stats* st) {
   st->probe_fail = s.band_fail;
   st->nonphysical = s.nonphys;
   st->first_bad = s.nonphys ? s.first_bad : -1;
+  st->surr_net = s.surr_net;
+  st->surr_exact = s.surr_exact;
   int rc = check_launch();
   if (rc) return rc;
   if (s.nonphys) return fail(RBDI_ERR_NONPHYSICAL, "a cell left the admissible set");
@@ -1245,6 +1289,205 @@ RBDI_API int rbdi_batch_autotune(rbdi_batch* b, int reps, rbdi_tuning* best) {
   rc = batch_build_items(b, ntask);
   if (rc) return rc;
   if (best) *best = bt;
+  return RBDI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Surrogate network (training, inference) and its use in the step
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void mlp_free(rbdi_mlp* m) {
+  void* ptrs[] = {m->blob, m->bias, m->master, m->m1, m->m2, m->sum};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  m->blob = nullptr; m->bias = nullptr; m->master = nullptr; m->m1 = nullptr; m->m2 = nullptr; m->sum = nullptr;
+}
+
+// Device copy of n x w host floats (caller frees).
+template <typename X>
+int upload(const X* src, size_t n, X** dst) {
+  *dst = nullptr;
+  if (n == 0) return RBDI_OK;
+  HIP_OK(hipMalloc((void**)dst, n * sizeof(X)));
+  HIP_OK(hipMemcpy(*dst, src, n * sizeof(X), hipMemcpyHostToDevice));
+  return RBDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+RBDI_API int rbdi_mlp_create(rbdi_mlp** out) {
+  if (!out) return fail(RBDI_ERR_BAD_ARG, "null out");
+  rbdi_mlp* m = new rbdi_mlp();
+  hipError_t e = hipMalloc((void**)&m->blob, sizeof(__bf16) * kBlobBf16);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->bias, sizeof(float) * kBiasN);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->master, sizeof(float) * kNParam);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->m1, sizeof(float) * kNParam);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->m2, sizeof(float) * kNParam);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->sum, sizeof(float) * (kNParam + 1));
+  if (e == hipSuccess) e = hipMemset(m->blob, 0, sizeof(__bf16) * kBlobBf16);
+  if (e == hipSuccess) e = hipMemset(m->bias, 0, sizeof(float) * kBiasN);
+  if (e == hipSuccess) e = hipMemset(m->master, 0, sizeof(float) * kNParam);
+  if (e == hipSuccess) e = hipMemset(m->m1, 0, sizeof(float) * kNParam);
+  if (e == hipSuccess) e = hipMemset(m->m2, 0, sizeof(float) * kNParam);
+  if (e != hipSuccess) {
+    mlp_free(m);
+    delete m;
+    return fail(RBDI_ERR_OOM, std::string("mlp allocation: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_mlp_destroy(rbdi_mlp* m) {
+  if (!m) return fail(RBDI_ERR_BAD_ARG, "null network");
+  (void)hipDeviceSynchronize();
+  mlp_free(m);
+  delete m;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_mlp_set_params(rbdi_mlp* m, const float* params, double tau_max) {
+  if (!m || !params) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (!(tau_max > 0.0) || !(tau_max < 1.0)) return fail(RBDI_ERR_BAD_ARG, "tau_max must be in (0, 1)");
+  for (int p = 0; p < kNParam; ++p)
+    if (!std::isfinite(params[p])) return fail(RBDI_ERR_BAD_ARG, "non-finite parameter");
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(m->master, params, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  HIP_OK(hipMemset(m->m1, 0, sizeof(float) * kNParam));
+  HIP_OK(hipMemset(m->m2, 0, sizeof(float) * kNParam));
+  m->tau_max = tau_max;
+  m->step = 0;
+  hipLaunchKernelGGL(k_mlp_sync, dim3((kNParam + 255) / 256), dim3(256), 0, nullptr, (const float*)m->master,
+                     m->blob, m->bias);
+  HIP_OK(hipDeviceSynchronize());
+  return check_launch();
+}
+
+RBDI_API int rbdi_mlp_get_params(rbdi_mlp* m, float* params, double* tau_max) {
+  if (!m || !params) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(params, m->master, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  if (tau_max) *tau_max = m->tau_max;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_mlp_forward(rbdi_mlp* m, const float* z, int n, float* y) {
+  if (!m || !z || !y || n < 0) return fail(RBDI_ERR_BAD_ARG, "bad mlp_forward argument");
+  if (n == 0) return RBDI_OK;
+  float *dz = nullptr, *dy = nullptr;
+  int rc = upload(z, (size_t)n * 6, &dz);
+  if (!rc && hipMalloc((void**)&dy, sizeof(float) * 6 * (size_t)n) != hipSuccess) rc = fail(RBDI_ERR_OOM, "mlp_forward");
+  if (!rc) {
+    hipLaunchKernelGGL(k_mlp_infer, dim3((n + 255) / 256), dim3(256), 0, nullptr, mlp_dev(m), (const float*)dz, dy, n);
+    if (hipMemcpy(y, dy, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(RBDI_ERR_HIP, "mlp_forward copy");
+    if (!rc) rc = check_launch();
+  }
+  if (dz) (void)hipFree(dz);
+  if (dy) (void)hipFree(dy);
+  return rc;
+}
+
+RBDI_API int rbdi_mlp_grad(rbdi_mlp* m, const float* z, const float* t, int n, float* grad, float* loss) {
+  if (!m || !z || !t || !grad || !loss || n < 1) return fail(RBDI_ERR_BAD_ARG, "bad mlp_grad argument");
+  const int nb = (n + 63) / 64;
+  float *dz = nullptr, *dt = nullptr, *part = nullptr;
+  int rc = upload(z, (size_t)n * 6, &dz);
+  if (!rc) rc = upload(t, (size_t)n * 6, &dt);
+  if (!rc && hipMalloc((void**)&part, sizeof(float) * (size_t)nb * (kNParam + 1)) != hipSuccess) rc = fail(RBDI_ERR_OOM, "mlp_grad");
+  if (!rc) {
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64), 0, nullptr, mlp_dev(m), (const float*)dz, (const float*)dt,
+                       0LL, n, n, part);
+    hipLaunchKernelGGL(k_mlp_sum, dim3((kNParam + 256) / 256), dim3(256), 0, nullptr, (const float*)part, nb, m->sum);
+    std::vector<float> h(kNParam + 1);
+    if (hipMemcpy(h.data(), m->sum, sizeof(float) * (kNParam + 1), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = fail(RBDI_ERR_HIP, "mlp_grad copy");
+    if (!rc) rc = check_launch();
+    if (!rc) {
+      std::memcpy(grad, h.data(), sizeof(float) * kNParam);
+      *loss = h[kNParam];
+    }
+  }
+  if (dz) (void)hipFree(dz);
+  if (dt) (void)hipFree(dt);
+  if (part) (void)hipFree(part);
+  return rc;
+}
+
+RBDI_API int rbdi_mlp_train(rbdi_mlp* m, const float* z, const float* t, int n, int batch, int iters, float lr,
+                            float* losses) {
+  if (!m || !z || !t || n < 1 || batch < 64 || iters < 0 || !(lr > 0.0f))
+    return fail(RBDI_ERR_BAD_ARG, "bad mlp_train argument");
+  if (batch % 64) return fail(RBDI_ERR_BAD_ARG, "batch must be a multiple of 64");
+  const int nb = batch / 64;
+  float *dz = nullptr, *dt = nullptr, *part = nullptr, *dl = nullptr;
+  int rc = upload(z, (size_t)n * 6, &dz);
+  if (!rc) rc = upload(t, (size_t)n * 6, &dt);
+  if (!rc && hipMalloc((void**)&part, sizeof(float) * (size_t)nb * (kNParam + 1)) != hipSuccess) rc = fail(RBDI_ERR_OOM, "mlp_train");
+  if (!rc && hipMalloc((void**)&dl, sizeof(float) * std::max(iters, 1)) != hipSuccess) rc = fail(RBDI_ERR_OOM, "mlp_train");
+  long long start = 0;
+  for (int it = 0; it < iters && !rc; ++it) {
+    // consecutive slices of the (caller-shuffled) samples, cyclically
+    if (start >= n) start = 0;
+    const int cnt = (int)std::min<long long>(batch, n - start);
+    const int nbi = (cnt + 63) / 64;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nbi), dim3(64), 0, nullptr, mlp_dev(m), (const float*)dz, (const float*)dt,
+                       start, cnt, cnt, part);
+    AdamArgs a;
+    a.lr = lr * 0.5f * (1.0f + cosf(3.14159265f * (float)it / (float)iters));
+    a.beta1 = 0.9f;
+    a.beta2 = 0.999f;
+    a.eps = 1e-8f;
+    a.step = ++m->step;
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kNParam + 256) / 256), dim3(256), 0, nullptr, (const float*)part, nbi,
+                       m->master, m->m1, m->m2, m->blob, m->bias, a, dl + it);
+    start += cnt;
+  }
+  if (!rc) rc = check_launch();
+  if (!rc && losses && iters > 0 &&
+      hipMemcpy(losses, dl, sizeof(float) * iters, hipMemcpyDeviceToHost) != hipSuccess)
+    rc = fail(RBDI_ERR_HIP, "mlp_train copy");
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(RBDI_ERR_HIP, "mlp_train sync");
+  if (dz) (void)hipFree(dz);
+  if (dt) (void)hipFree(dt);
+  if (part) (void)hipFree(part);
+  if (dl) (void)hipFree(dl);
+  return rc;
+}
+
+RBDI_API int rbdi_mlp_data(const double* V, int n, double tau_max, float* z, float* t) {
+  if (!V || !z || !t || n < 0 || !(tau_max > 0.0)) return fail(RBDI_ERR_BAD_ARG, "bad mlp_data argument");
+  if (n == 0) return RBDI_OK;
+  double* dV = nullptr;
+  float *dz = nullptr, *dt = nullptr;
+  int rc = upload(V, (size_t)n * 9, &dV);
+  if (!rc && (hipMalloc((void**)&dz, sizeof(float) * 6 * (size_t)n) != hipSuccess ||
+              hipMalloc((void**)&dt, sizeof(float) * 6 * (size_t)n) != hipSuccess))
+    rc = fail(RBDI_ERR_OOM, "mlp_data");
+  if (!rc) {
+    hipLaunchKernelGGL(k_mlp_data, dim3((n + 255) / 256), dim3(256), 0, nullptr, (const double*)dV, n, tau_max, dz, dt);
+    if (hipMemcpy(z, dz, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(t, dt, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = fail(RBDI_ERR_HIP, "mlp_data copy");
+    if (!rc) rc = check_launch();
+  }
+  if (dV) (void)hipFree(dV);
+  if (dz) (void)hipFree(dz);
+  if (dt) (void)hipFree(dt);
+  return rc;
+}
+
+RBDI_API int rbdi_set_surrogate(rbdi_handle* h, rbdi_mlp* m) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
+  if (m && !h->desc.solid) return fail(RBDI_ERR_UNSUPPORTED, "the surrogate closes the elastoplastic system only");
+  h->mlp = m;
+  h->P.surr = m ? 1 : 0;
   return RBDI_OK;
 }
 

@@ -42,6 +42,8 @@ struct DevScalars {
   int band_count;     // seeding tasks of the current band
   int band_fail;      // band cells without a valid probe
   int npart;          // CFL partials written by their last producer
+  long long surr_net;    // plastic-return cells closed by the surrogate
+  long long surr_exact;  // ... by the exact closure (outside its envelope / flagged)
 };
 
 // Host-side arguments of one step.
@@ -296,9 +298,9 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   // cache lines shared by neighbouring segments are fetched once
   const int seg = bx * wpb + wave, j = by, k = bz;
   const size_t part_slot = (size_t)blin * wpb + wave;
-  if (stage == 2 && blin == 0 && threadIdx.x == 0) sc->npart = nparts;
+  if (stage == 2 && blin == 0 && threadIdx.x == 0 && !P.surr) sc->npart = nparts;
   if (seg * kOut >= P.n[0]) {  // whole wavefront beyond the row
-    if (stage == 2 && lane == 0) cflpart[part_slot] = 0.0;
+    if (stage == 2 && lane == 0 && !P.surr) cflpart[part_slot] = 0.0;
     return;
   }
   const int nd = P.n[0];
@@ -351,7 +353,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
       }
     }
     if constexpr (S::S) {
-      if (!rigid) solid_sources<S>(P, Un);
+      if (!rigid && !P.surr) solid_sources<S>(P, Un);
     }
     bool ok = true;
 #pragma unroll
@@ -362,7 +364,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     }
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = Un[q];
-    if (stage == 2 && !((double)Un[S::R] > 0.5)) {
+    if (stage == 2 && !P.surr && !((double)Un[S::R] > 0.5)) {
       double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pc[a] + 0.5) * P.dx[a];
@@ -370,7 +372,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
       rate = cfl_rate<S>(P, Un, x, tc + dt);
     }
   }
-  if (stage == 2) {
+  if (stage == 2 && !P.surr) {
     for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
     if (lane == 0) cflpart[part_slot] = rate;
   }

@@ -59,6 +59,8 @@ struct Params {
   double lm_mach;
   int solid_phase;
   int r_static;           // rigid velocity identically zero: r never changes
+  int surr;               // elastoplastic sources (and the CFL partials of the
+                          // last stage) by the separate surrogate pass
   MatDev mat[kMaxMat];
   double vr[3], om[3], ctr[3];
   double bcW[6][kMaxF];   // Dirichlet primitive states per face
@@ -139,10 +141,66 @@ __device__ inline void jacobi3(T A[3][3], T Q[3][3]) {
   }
 }
 
+// Isotropic matrix functions without an eigen-decomposition. For a
+// symmetric 3x3 matrix A with principal invariants i1, i2, i3, the
+// Cayley-Hamilton theorem A^3 = i1 A^2 - i2 A + i3 I keeps every power in the
+// span of I, A, A^2: if A^k = al I + be A + ga A^2 then
+// A^(k+1) = ga i3 I + (al - ga i2) A + (be + ga i1) A^2. A power series
+// f(A) = sum_k w_k A^k is therefore c0 I + c1 A + c2 A^2 with the sums of
+// w_k (al, be, ga). Used for ln(I + X) and exp(A) at small |X|, |A|, where
+// the series converge fast; the same functions by eigen-decomposition remain
+// the fallback for large arguments.
+struct SymM {
+  double a00, a11, a22, a01, a02, a12;
+};
+
+__device__ inline SymM sym_sq(const SymM& x) {
+  SymM q;
+  q.a00 = x.a00 * x.a00 + x.a01 * x.a01 + x.a02 * x.a02;
+  q.a11 = x.a01 * x.a01 + x.a11 * x.a11 + x.a12 * x.a12;
+  q.a22 = x.a02 * x.a02 + x.a12 * x.a12 + x.a22 * x.a22;
+  q.a01 = x.a00 * x.a01 + x.a01 * x.a11 + x.a02 * x.a12;
+  q.a02 = x.a00 * x.a02 + x.a01 * x.a12 + x.a02 * x.a22;
+  q.a12 = x.a01 * x.a02 + x.a11 * x.a12 + x.a12 * x.a22;
+  return q;
+}
+
+// Power series coefficients: w_k for k >= 1 from a table (terms until the
+// k-th term is below 1e-17 of the first), returns (c0, c1, c2) for
+// sum_{k>=1} w_k A^k; t = Frobenius norm of A (bounds its spectral radius),
+// first = |w_1| t, the scale of the leading term.
+template <int KMAX, typename WF>
+__device__ inline void ch_series(const SymM& A, double t, WF wk, double& c0, double& c1, double& c2) {
+  const double i1 = A.a00 + A.a11 + A.a22;
+  const double t2 = t * t;
+  const double i2 = 0.5 * (i1 * i1 - t2);
+  const double i3 = A.a00 * (A.a11 * A.a22 - A.a12 * A.a12) - A.a01 * (A.a01 * A.a22 - A.a12 * A.a02) +
+                    A.a02 * (A.a01 * A.a12 - A.a11 * A.a02);
+  double al = 0.0, be = 1.0, ga = 0.0;
+  c0 = 0.0;
+  c1 = 0.0;
+  c2 = 0.0;
+  const double lead = fabs(wk(1)) * t;
+  for (int k = 1; k <= KMAX; ++k) {
+    const double w = wk(k);
+    c0 += w * al;
+    c1 += w * be;
+    c2 += w * ga;
+    const double mag = fabs(w) * (fabs(al) + fabs(be) * t + fabs(ga) * t2);
+    if (k > 1 && mag <= 1e-17 * lead) break;
+    const double nal = ga * i3, nbe = al - ga * i2, nga = be + ga * i1;
+    al = nal;
+    be = nbe;
+    ga = nga;
+  }
+}
+
+__device__ inline double log_w(int k) { return (k & 1 ? 0.5 : -0.5) / (double)k; }
+
 // Hencky strain H = (1/2) ln(Vbar Vbar^T) (equals ln Vbar for a symmetric
-// stretch; Sec. 2.1.2) and J2 = H:H.
+// stretch; Sec. 2.1.2) and J2 = H:H, by eigen-decomposition.
 template <typename T>
-__device__ inline void hencky3(const T V[9], T H[9], T& J2) {
+__device__ __attribute__((noinline)) void hencky3_eig(const T V[9], T H[9], T& J2) {
   T b[3][3], Q[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -162,6 +220,34 @@ __device__ inline void hencky3(const T V[9], T H[9], T& J2) {
       H[3 * i + j] = v;
       J2 += v * v;
     }
+}
+
+// The same H and J2: for |X| <= 0.3 (X = Vbar Vbar^T - I) by the series of
+// (1/2) ln(I + X), otherwise by eigen-decomposition.
+template <typename T>
+__device__ inline void hencky3(const T V[9], T H[9], T& J2) {
+  SymM X;
+  X.a00 = (double)(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) - 1.0;
+  X.a11 = (double)(V[3] * V[3] + V[4] * V[4] + V[5] * V[5]) - 1.0;
+  X.a22 = (double)(V[6] * V[6] + V[7] * V[7] + V[8] * V[8]) - 1.0;
+  X.a01 = (double)(V[0] * V[3] + V[1] * V[4] + V[2] * V[5]);
+  X.a02 = (double)(V[0] * V[6] + V[1] * V[7] + V[2] * V[8]);
+  X.a12 = (double)(V[3] * V[6] + V[4] * V[7] + V[5] * V[8]);
+  const SymM X2 = sym_sq(X);
+  const double t2 = X2.a00 + X2.a11 + X2.a22;
+  if (!(t2 <= 0.09)) {
+    hencky3_eig(V, H, J2);
+    return;
+  }
+  double c0, c1, c2;
+  ch_series<64>(X, sqrt(t2), log_w, c0, c1, c2);
+  const double h00 = c0 + c1 * X.a00 + c2 * X2.a00, h11 = c0 + c1 * X.a11 + c2 * X2.a11;
+  const double h22 = c0 + c1 * X.a22 + c2 * X2.a22, h01 = c1 * X.a01 + c2 * X2.a01;
+  const double h02 = c1 * X.a02 + c2 * X2.a02, h12 = c1 * X.a12 + c2 * X2.a12;
+  H[0] = (T)h00; H[1] = (T)h01; H[2] = (T)h02;
+  H[3] = (T)h01; H[4] = (T)h11; H[5] = (T)h12;
+  H[6] = (T)h02; H[7] = (T)h12; H[8] = (T)h22;
+  J2 = (T)(h00 * h00 + h11 * h11 + h22 * h22 + 2.0 * (h01 * h01 + h02 * h02 + h12 * h12));
 }
 
 // ---------------------------------------------------------------------------
@@ -740,6 +826,47 @@ __device__ inline void riemann_seed(const Params& P, const double* Wm, const dou
 // through Vbar <- exp((s-1) H) Vbar; eps_p grows by sqrt(2/3)(1-s)|H|;
 // rho E unchanged).
 // ---------------------------------------------------------------------------
+__device__ inline double exp_w(int k) {
+  double f = 1.0;
+  for (int j = 2; j <= k; ++j) f *= (double)j;
+  return 1.0 / f;
+}
+
+// E = exp(a H) for symmetric H: by eigen-decomposition.
+__device__ __attribute__((noinline)) void plastic_exp_eig(double a, const double* H, double* E) {
+  double A[3][3], Q[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = a * H[3 * i + j];
+  jacobi3(A, Q);
+  double ev[3];
+  for (int k = 0; k < 3; ++k) ev[k] = exp(A[k][k]);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) E[3 * i + j] = Q[i][0] * ev[0] * Q[j][0] + Q[i][1] * ev[1] * Q[j][1] + Q[i][2] * ev[2] * Q[j][2];
+}
+
+// E = exp(a H): the exponential series for |a H| <= 1, else by
+// eigen-decomposition.
+__device__ inline void plastic_exp(double a, const double* H, double* E) {
+  SymM A;
+  A.a00 = a * H[0]; A.a11 = a * H[4]; A.a22 = a * H[8];
+  A.a01 = a * H[1]; A.a02 = a * H[2]; A.a12 = a * H[5];
+  const SymM A2 = sym_sq(A);
+  const double t2 = A2.a00 + A2.a11 + A2.a22;
+  if (!(t2 <= 1.0)) {
+    plastic_exp_eig(a, H, E);
+    return;
+  }
+  double c0, c1, c2;
+  ch_series<40>(A, sqrt(t2), exp_w, c0, c1, c2);
+  c0 += 1.0;  // the k = 0 term
+  E[0] = c0 + c1 * A.a00 + c2 * A2.a00;
+  E[4] = c0 + c1 * A.a11 + c2 * A2.a11;
+  E[8] = c0 + c1 * A.a22 + c2 * A2.a22;
+  E[1] = E[3] = c1 * A.a01 + c2 * A2.a01;
+  E[2] = E[6] = c1 * A.a02 + c2 * A2.a02;
+  E[5] = E[7] = c1 * A.a12 + c2 * A2.a12;
+}
+
 template <class S, typename T>
 __device__ inline void solid_sources(const Params& P, T* U) {
   double V[9];
@@ -766,21 +893,9 @@ __device__ inline void solid_sources(const Params& P, T* U) {
     const double seq = 2.449489742783178 * G * Hn;
     if (sY > 0.0 && seq > sY) {
       const double s = sY / seq;
-      // exp((s-1) H) by the eigenvectors of H
-      double A[3][3], Q[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) A[a][b] = (s - 1.0) * H[3 * a + b];
-      jacobi3(A, Q);
-      double ev[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) ev[k] = exp(A[k][k]);
+      // exp((s-1) H)
       double X[9], Vn[9];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) X[3 * a + b] = Q[a][0] * ev[0] * Q[b][0] + Q[a][1] * ev[1] * Q[b][1] + Q[a][2] * ev[2] * Q[b][2];
+      plastic_exp(s - 1.0, H, X);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll

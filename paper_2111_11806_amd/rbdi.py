@@ -56,7 +56,8 @@ class Tuning(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
                 ("band_cells", ctypes.c_longlong), ("seeded", ctypes.c_longlong),
-                ("probe_fail", ctypes.c_longlong), ("nonphysical", ctypes.c_int), ("first_bad", ctypes.c_longlong)]
+                ("probe_fail", ctypes.c_longlong), ("nonphysical", ctypes.c_int), ("first_bad", ctypes.c_longlong),
+                ("surr_net", ctypes.c_longlong), ("surr_exact", ctypes.c_longlong)]
 
 
 _lib = None
@@ -65,11 +66,15 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
            "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
-           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs", "rbdi_kernel_replay",
+           "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
+           "rbdi_kernel_replay",
            "rbdi_batch_create", "rbdi_batch_destroy", "rbdi_batch_set_stream", "rbdi_batch_set_tuning",
-           "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance"]
-NUM_KCLASS = 6
-KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt"]
+           "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance",
+           "rbdi_mlp_create", "rbdi_mlp_destroy", "rbdi_mlp_set_params", "rbdi_mlp_get_params", "rbdi_mlp_data",
+           "rbdi_mlp_forward", "rbdi_mlp_grad", "rbdi_mlp_train", "rbdi_set_surrogate"]
+NUM_KCLASS = 7
+KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt", "sources_mlp"]
+N_MLP_PARAMS = 9158
 
 
 def lib_path():
@@ -116,6 +121,16 @@ def load():
     L.rbdi_batch_autotune.argtypes = [vp, ip, ctypes.POINTER(Tuning)]
     L.rbdi_batch_step.argtypes = [vp, ctypes.c_double, dp]
     L.rbdi_batch_advance.argtypes = [vp, ctypes.c_double, ip, ctypes.c_double]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.rbdi_mlp_create.argtypes = [ctypes.POINTER(vp)]
+    L.rbdi_mlp_destroy.argtypes = [vp]
+    L.rbdi_mlp_set_params.argtypes = [vp, fp, ctypes.c_double]
+    L.rbdi_mlp_get_params.argtypes = [vp, fp, dp]
+    L.rbdi_mlp_data.argtypes = [dp, ip, ctypes.c_double, fp, fp]
+    L.rbdi_mlp_forward.argtypes = [vp, fp, ip, fp]
+    L.rbdi_mlp_grad.argtypes = [vp, fp, fp, ip, fp, fp]
+    L.rbdi_mlp_train.argtypes = [vp, fp, fp, ip, ip, ip, ctypes.c_float, fp]
+    L.rbdi_set_surrogate.argtypes = [vp, vp]
     _lib = L
     return L
 
@@ -329,6 +344,11 @@ class Solver:
         for dt in dts:
             self.step(dt)
 
+    def set_surrogate(self, mlp):
+        """Close the elastoplastic sources with the network (None: exact)."""
+        self._mlp = mlp
+        _check(load().rbdi_set_surrogate(self._h, None if mlp is None else mlp._m))
+
 
 def _tuning_dict(t):
     return {k: getattr(t, k) for k, _ in Tuning._fields_}
@@ -392,3 +412,79 @@ class Batch:
 
     def advance(self, cfl, nsteps, t_end=0.0):
         _check(load().rbdi_batch_advance(self._b, float(cfl), int(nsteps), float(t_end)))
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _f32(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def mlp_data(V, tau_max):
+    """Features z and exact targets t (n x 6 each) of stretch tensors V (n x 9)."""
+    V = _arr(V).reshape(-1, 9)
+    n = V.shape[0]
+    z = np.zeros((n, 6), np.float32)
+    t = np.zeros((n, 6), np.float32)
+    _check(load().rbdi_mlp_data(_dp(V), n, float(tau_max), _fp(z), _fp(t)))
+    return z, t
+
+
+class Mlp:
+    """The surrogate network (rbdi_mlp_*)."""
+
+    def __init__(self, params=None, tau_max=0.01):
+        L = load()
+        m = ctypes.c_void_p()
+        _check(L.rbdi_mlp_create(ctypes.byref(m)))
+        self._m = m
+        if params is not None:
+            self.set_params(params, tau_max)
+
+    def close(self):
+        m = getattr(self, "_m", None)
+        if m:
+            load().rbdi_mlp_destroy(m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, tau_max):
+        _check(load().rbdi_mlp_set_params(self._m, _fp(_f32(params, N_MLP_PARAMS)), float(tau_max)))
+
+    def params(self):
+        p = np.zeros(N_MLP_PARAMS, np.float32)
+        tm = ctypes.c_double()
+        _check(load().rbdi_mlp_get_params(self._m, _fp(p), ctypes.byref(tm)))
+        return p, tm.value
+
+    def forward(self, z):
+        z = _f32(z).reshape(-1, 6)
+        y = np.zeros_like(z)
+        _check(load().rbdi_mlp_forward(self._m, _fp(z), z.shape[0], _fp(y)))
+        return y
+
+    def grad(self, z, t):
+        z = _f32(z).reshape(-1, 6)
+        t = _f32(t).reshape(-1, 6)
+        g = np.zeros(N_MLP_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _check(load().rbdi_mlp_grad(self._m, _fp(z), _fp(t), z.shape[0], _fp(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, z, t, batch=4096, iters=1000, lr=1e-3):
+        z = _f32(z).reshape(-1, 6)
+        t = _f32(t).reshape(-1, 6)
+        losses = np.zeros(iters, np.float32)
+        _check(load().rbdi_mlp_train(self._m, _fp(z), _fp(t), z.shape[0], int(batch), int(iters), float(lr),
+                                     _fp(losses)))
+        return losses
