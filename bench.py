@@ -16,6 +16,7 @@ relative L1 difference from the FP64 path after a common fixed-dt sequence.
 from __future__ import annotations
 
 import argparse
+import numpy as np
 import json
 import os
 import sys
@@ -166,6 +167,45 @@ def run_batched(steps, warmup, precision="fp32"):
             "tuning": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()}}
 
 
+def run_copper(n, steps, warmup):
+    """3D copper indenter (n^3): plain FP64 (exact closure) against FP32 with
+    the surrogate closure, and the two mixed variants; the network is trained
+    first on the solver's own stretches (32^3 run) by the library's kernels."""
+    import torch
+    from paper_2111_11806_amd import inputs, rbdi, surrogate
+    t0 = time.perf_counter()
+    V = surrogate.generate(inputs.copper_indenter(32), steps=40, every=10)
+    net, info = surrogate.train(V, iters=1500, batch=4096, lr=2e-3, seed=0)
+    train_s = time.perf_counter() - t0
+    prob = inputs.copper_indenter(n)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "copper_indenter", "n": n, "cells": prob.ncells, "steps": steps,
+           "training": {"samples": info["samples"], "tau_max": info["tau_max"], "iters": len(info["losses"]),
+                        "final_loss": float(np.mean(info["losses"][-20:])), "seconds": round(train_s, 2)}}
+    for name, prec, surr in (("fp64_exact", "fp64", False), ("fp32_surrogate", "fp32", True),
+                             ("fp32_exact", "fp32", False), ("fp64_surrogate", "fp64", True)):
+        s = rbdi.Solver(prob, prec, stream=stream)
+        if surr:
+            s.set_surrogate(net)
+        s.advance(prob.cfl, warmup, prob.t_end)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.advance(prob.cfl, steps, prob.t_end)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = s.status(raise_on_error=False)
+        out[name] = {"ms_per_step": round(ms, 3), "value": prob.ncells / (ms * 1e-3),
+                     "nonphysical": st["nonphysical"], "surrogate_cells": st["surr_net"],
+                     "exact_fallback_cells": st["surr_exact"]}
+        s.close()
+        del s
+    out["speedup_fp32_surrogate_vs_fp64"] = out["fp64_exact"]["ms_per_step"] / out["fp32_surrogate"]["ms_per_step"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +218,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copper-n", type=int, default=256)
+    ap.add_argument("--copper-steps", type=int, default=5)
+    ap.add_argument("--no-copper", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -254,6 +297,9 @@ def main():
 
     if not args.no_batch:
         out["batched"] = run_batched(args.batch_steps, 10)
+
+    if not args.no_copper:
+        out["copper"] = run_copper(args.copper_n, args.copper_steps, 2)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -1,0 +1,111 @@
+"""Parity at the full sizes of the workloads, in the launch configuration the
+benchmark times (device CFL steps by rbdi_advance where the benchmark uses
+them), against the CPU FP64 oracle:
+
+- Mach 2.8 shock over a rigid cylinder, 1024 x 512 (FP64 <= 1e-10, FP32
+  <= 1e-4 relative L1 per conserved field);
+- air/water with a moving rigid ellipse, 2048 x 1024 (FP64 <= 1e-10);
+- 3D copper indenter, 256^3, one step (FP64 <= 1e-10; FP32 with the
+  surrogate closure <= 1e-4 per quantity, vectors and tensors whole).
+
+The 64-instance batch at full size is covered in test_gpu_batch.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_11806_amd import inputs
+from parity_util import announce, rel_l1, rel_l1_grouped
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rbdi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2111_11806_amd import rbdi as r
+    r.load()
+    return r
+
+
+def test_shock_cylinder_full_size_fp64_device_dt(rbdi):
+    """300 device-CFL steps: the shock has reached and wrapped the body."""
+    prob = inputs.shock_cylinder(1024, 512)
+    announce("shock_cylinder 1024x512 fp64, 300 device-CFL steps")
+    orc = oracle.Oracle(prob)
+    orc.run(nsteps=300)
+    s = rbdi.Solver(prob, "fp64")
+    s.advance(prob.cfl, 300, prob.t_end)
+    st = s.status()
+    assert st["steps"] == 300 and abs(st["t"] - orc.t) <= 1e-12 * orc.t
+    rl = rel_l1(s.get_state_cons(), orc.get_state_cons())
+    announce("  rel L1 " + np.array2string(rl, precision=2))
+    assert np.all(rl <= 1e-10), rl
+    F, T = s.rigid_force((0.3, 0.25, 0.0))
+    Fo, To = orc.rigid_force((0.3, 0.25, 0.0))
+    announce(f"  force gpu {F} oracle {Fo}")
+    assert abs(Fo[0]) > 1e-3  # the shock loads the body
+    # the transverse component vanishes by symmetry up to summation rounding
+    assert np.linalg.norm(F - Fo) <= 1e-10 * np.linalg.norm(Fo)
+
+
+def test_shock_cylinder_full_size_fp32(rbdi):
+    prob = inputs.shock_cylinder(1024, 512)
+    announce("shock_cylinder 1024x512 fp32, 20 oracle-dt steps")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(nsteps=20)
+    s = rbdi.Solver(prob, "fp32")
+    s.run(dts)
+    rl = rel_l1(s.get_state_cons(), orc.get_state_cons())
+    announce("  rel L1 " + np.array2string(rl, precision=2))
+    assert np.all(rl <= 1e-4), rl
+
+
+def test_air_water_full_size_fp64(rbdi):
+    prob = inputs.air_water(2048, 1024)
+    announce("air_water 2048x1024 fp64, 5 steps")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(nsteps=5)
+    s = rbdi.Solver(prob, "fp64")
+    s.run(dts)
+    assert s.status()["nonphysical"] == 0
+    rl = rel_l1(s.get_state_cons(), orc.get_state_cons())
+    announce("  rel L1 " + np.array2string(rl, precision=2))
+    assert np.all(rl <= 1e-10), rl
+
+
+@pytest.fixture(scope="module")
+def copper_ref():
+    prob = inputs.copper_indenter(256)
+    announce("copper_indenter 256^3: oracle, 1 step")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(nsteps=1)
+    return prob, dts, orc.get_state_cons()
+
+
+def test_copper_indenter_full_size_fp64(rbdi, copper_ref):
+    prob, dts, U0 = copper_ref
+    announce("copper_indenter 256^3 fp64, 1 step")
+    s = rbdi.Solver(prob, "fp64")
+    s.run(dts)
+    assert s.status()["nonphysical"] == 0
+    rl = rel_l1(s.get_state_cons(), U0)
+    announce("  rel L1 " + np.array2string(rl, precision=2))
+    assert np.all(rl <= 1e-10), rl
+
+
+def test_copper_indenter_full_size_fp32_surrogate(rbdi, copper_ref):
+    from paper_2111_11806_amd import surrogate
+    prob, dts, U0 = copper_ref
+    V = surrogate.generate(inputs.copper_indenter(32), steps=40, every=10)
+    net, info = surrogate.train(V, iters=1500, batch=4096, lr=2e-3, seed=0)
+    announce("copper_indenter 256^3 fp32 + surrogate, 1 step (tau_max %.2e)" % info["tau_max"])
+    s = rbdi.Solver(prob, "fp32")
+    s.set_surrogate(net)
+    s.run(dts)
+    st = s.status()
+    assert st["nonphysical"] == 0 and st["surr_net"] > 0
+    rg = rel_l1_grouped(s.get_state_cons(), U0, prob)
+    announce("  rel L1 per quantity " + ", ".join("%s %.2e" % kv for kv in rg.items()))
+    assert max(rg.values()) <= 1e-4, rg
