@@ -240,7 +240,9 @@ RBDI_API int rbdi_unit_eval(rbdi_handle* h, int what, int dir, const double* a, 
 /* The semi-discrete operator D(U) of the current state (Sec. 3.1, spatial
  * operator; no seeding; thermodynamic rows of rigid cells are not used by a
  * step), host FP64 [nfields][cells], summed over the directions whose bit is
- * set in dirmask (bit d = direction d; 7 = all). Diagnostic: overwrites the
+ * set in dirmask (bit d = direction d; 7 = all). The energy row is that of the
+ * stored energy E~ = rho E - B(phi), B(phi) = sum_l phi_l gamma_l p_inf,l /
+ * (gamma_l - 1) (equal to rho E's row without stiffened phases). Diagnostic: overwrites the
  * handle's stage buffers; synchronises. */
 RBDI_API int rbdi_eval_rhs(rbdi_handle* h, int dirmask, double* D);
 

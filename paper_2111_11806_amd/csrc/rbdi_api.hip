@@ -137,7 +137,7 @@ MlpDev mlp_dev(const rbdi_mlp* m) {
 struct Ops {
   void (*prim_to_state)(rbdi_handle*, const double*);
   void (*state_to_prim)(rbdi_handle*, double*);
-  void (*state_to_f64)(rbdi_handle*, double*);
+  void (*state_to_f64)(rbdi_handle*, double*, int);
   void (*f64_to_state)(rbdi_handle*, const double*);
   void (*r_from_sdf)(rbdi_handle*, const double*, double);
   void (*band)(rbdi_handle*, const StepArgs&);
@@ -166,9 +166,9 @@ struct Impl {
     hipLaunchKernelGGL((k_state_to_prim<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
                        (const T*)u(h, 0), W);
   }
-  static void state_to_f64(rbdi_handle* h, double* out) {
+  static void state_to_f64(rbdi_handle* h, double* out, int add_B) {
     hipLaunchKernelGGL((k_state_to_f64<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
-                       (const T*)u(h, 0), out);
+                       (const T*)u(h, 0), out, add_B);
   }
   static void f64_to_state(rbdi_handle* h, const double* in) {
     hipLaunchKernelGGL((k_f64_to_state<S, T>), dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->stream, h->P,
@@ -509,6 +509,9 @@ RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* e) {
   }
   h->P.mat[l] = m;
   h->have_mat[l] = true;
+  h->P.stiff = 0;
+  for (int k = 0; k < kMaxMat; ++k)
+    if (h->P.mat[k].Bfl != 0.0) h->P.stiff = 1;
   return RBDI_OK;
 }
 
@@ -585,7 +588,7 @@ RBDI_API int rbdi_get_state_prim(rbdi_handle* h, double* W, int on_device) {
 RBDI_API int rbdi_get_state_cons(rbdi_handle* h, double* U, int on_device) {
   if (!h || !U) return fail(RBDI_ERR_BAD_ARG, "null argument");
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
-  h->ops->state_to_f64(h, h->stage_buf);
+  h->ops->state_to_f64(h, h->stage_buf, 1);
   return stage_out(h, U, on_device);
 }
 
@@ -720,7 +723,7 @@ RBDI_API int rbdi_eval_rhs(rbdi_handle* h, int dirmask, double* D) {
   h->ops->rhs(h, dirmask);
   // D sits in state buffer 1; convert it through the staging buffer
   std::swap(h->U[0], h->U[1]);
-  h->ops->state_to_f64(h, h->stage_buf);
+  h->ops->state_to_f64(h, h->stage_buf, 0);
   std::swap(h->U[0], h->U[1]);
   const size_t bytes = (size_t)h->P.ncell * h->nf * sizeof(double);
   HIP_OK(hipMemcpyAsync(D, h->stage_buf, bytes, hipMemcpyDeviceToHost, h->stream));

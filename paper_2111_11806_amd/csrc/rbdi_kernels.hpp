@@ -247,6 +247,11 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
   const T du = us - usm;
 #pragma unroll
   for (int l = 0; l < S::N - 1; ++l) d[S::cPHI(l)] -= W[S::wPHI(l)] * du * inv;
+  if (P.stiff) {  // the energy slot holds E~ = rho E - B(phi)
+    double phi[kMaxMat], rl[kMaxMat];
+    phases_w<S>(W, phi, rl);
+    d[S::cE] += (T)(mix_B<S>(P, phi) * (double)(du * inv));
+  }
   if constexpr (S::S) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -834,9 +839,12 @@ __global__ __launch_bounds__(kRedThreads) void k_totals_partial(Params P, const 
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
        c += (long long)gridDim.x * blockDim.x) {
     const bool rig = (double)U[S::R * P.fs + c] > 0.5;
+    T Uc[S::NF];
+    load_cons<S>(P, U, c, Uc);
+    const double Bc = mix_B_cons<S>(P, Uc);
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) {
-      const double v = (double)U[q * P.fs + c] * dV;
+      const double v = ((double)Uc[q] + (q == S::cE ? Bc : 0.0)) * dV;
       all[q] += v;
       flu[q] += rig ? 0.0 : v;
     }
@@ -888,19 +896,26 @@ __global__ void k_state_to_prim(Params P, const T* __restrict__ U, double* __res
 }
 
 template <class S, typename T>
-__global__ void k_state_to_f64(Params P, const T* __restrict__ U, double* __restrict__ out) {
+__global__ void k_state_to_f64(Params P, const T* __restrict__ U, double* __restrict__ out, int add_B) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
+  T Uc[S::NF];
+  load_cons<S>(P, U, c, Uc);
 #pragma unroll
-  for (int q = 0; q < S::NF; ++q) out[q * P.ncell + c] = (double)U[q * P.fs + c];
+  for (int q = 0; q < S::NF; ++q) out[q * P.ncell + c] = (double)Uc[q];
+  if (add_B) out[S::cE * P.ncell + c] += mix_B_cons<S>(P, Uc);  // rho E = E~ + B(phi)
 }
 
 template <class S, typename T>
 __global__ void k_f64_to_state(Params P, const double* __restrict__ in, T* __restrict__ U) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
+  double Ud[S::NF];
 #pragma unroll
-  for (int q = 0; q < S::NF; ++q) U[q * P.fs + c] = (T)in[q * P.ncell + c];
+  for (int q = 0; q < S::NF; ++q) Ud[q] = in[q * P.ncell + c];
+  Ud[S::cE] -= mix_B_cons<S>(P, Ud);  // E~ = rho E - B(phi)
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) U[q * P.fs + c] = (T)Ud[q];
 }
 
 // r = (1 - tanh(sdf / (width dx_min))) / 2 (bodies as a diffuse scalar field).
@@ -928,6 +943,11 @@ __global__ void k_unit_flux(Params P, const double* __restrict__ WL, const doubl
   double* o = out + (size_t)i * (S::NT + 4);
 #pragma unroll
   for (int q = 0; q < S::NT; ++q) o[q] = (double)F[q];
+  // flux of rho E = flux of E~ + B_N (unit-field flux) + sum_l (B_l - B_N) F(phi_l)
+  const double BN = P.mat[S::N - 1].Bfl;
+  o[S::cE] += BN * (double)us;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) o[S::cE] += (P.mat[l].Bfl - BN) * (double)F[S::cPHI(l)];
   o[S::NT] = (double)us;
   for (int b = 0; b < 3; ++b) o[S::NT + 1 + b] = (double)Vs[b];
 }
@@ -940,6 +960,7 @@ __global__ void k_unit_closure(Params P, const double* __restrict__ U, double* _
   T Uc[S::NF], W[S::NF];
 #pragma unroll
   for (int q = 0; q < S::NF; ++q) Uc[q] = (T)U[i * S::NF + q];
+  Uc[S::cE] = (T)(U[i * S::NF + S::cE] - mix_B_cons<S>(P, U + (size_t)i * S::NF));
   double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, J2 = 0.0;
   cons_to_prim<S>(P, Uc, W, H, &J2);
   double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
@@ -961,9 +982,12 @@ __global__ void k_unit_sources(Params P, double* __restrict__ U, int n) {
   T Uc[S::NF];
 #pragma unroll
   for (int q = 0; q < S::NF; ++q) Uc[q] = (T)U[i * S::NF + q];
+  const double B = mix_B_cons<S>(P, U + (size_t)i * S::NF);
+  Uc[S::cE] = (T)(U[i * S::NF + S::cE] - B);
   if constexpr (S::S) solid_sources<S>(P, Uc);
 #pragma unroll
   for (int q = 0; q < S::NF; ++q) U[i * S::NF + q] = (double)Uc[q];
+  U[i * S::NF + S::cE] = (double)Uc[S::cE] + B;
 }
 
 }  // namespace rbdi

@@ -59,6 +59,7 @@ struct Params {
   double lm_mach;
   int solid_phase;
   int r_static;           // rigid velocity identically zero: r never changes
+  int stiff;              // some phase has a stiffening energy (B(phi) != 0)
   int surr;               // elastoplastic sources (and the CFL partials of the
                           // last stage) by the separate surrogate pass
   MatDev mat[kMaxMat];
@@ -281,19 +282,17 @@ __device__ inline void romenskii_ref(const MatDev& m, double rho, double J2, dou
 // p = [rho e - sum phi_l B_l] / sum(phi_l / Gamma_l).
 template <class S>
 __device__ inline double mix_pressure(const Params& P, const double* phi, const double* rho, double J2,
-                                      double rhoe) {
-  if constexpr (S::N == 1 && !S::S) return (rhoe - P.mat[0].Bfl) * P.mat[0].Gam;
-  double num = rhoe, den = 0.0;
+                                      double rhoe_t) {
+  if constexpr (S::N == 1 && !S::S) return rhoe_t * P.mat[0].Gam;
+  double num = rhoe_t, den = 0.0;
 #pragma unroll
   for (int l = 0; l < S::N; ++l) {
     const MatDev& m = P.mat[l];
-    double B = m.Bfl;
     if (S::S && m.kind == EOS_ROMENSKII) {
       double er, pr, dp, G;
       romenskii_ref(m, rho[l], J2, er, pr, dp, G);
-      B = er - pr * m.invGam;
+      num -= phi[l] * (er - pr * m.invGam);
     }
-    num -= phi[l] * B;
     den += phi[l] * m.invGam;
   }
   return num * frcp(den);
@@ -306,16 +305,44 @@ __device__ inline double mix_rhoe(const Params& P, const double* phi, const doub
 #pragma unroll
   for (int l = 0; l < S::N; ++l) {
     const MatDev& m = P.mat[l];
-    double B = m.Bfl;
     if (S::S && m.kind == EOS_ROMENSKII) {
       double er, pr, dp, G;
       romenskii_ref(m, rho[l], J2, er, pr, dp, G);
-      B = er - pr * m.invGam;
+      s += phi[l] * (er - pr * m.invGam);
     }
-    s += phi[l] * B;
     den += phi[l] * m.invGam;
   }
   return p * den + s;
+}
+
+// Stiffening energy of the mixture, B(phi) = sum_l phi_l gamma_l p_inf,l /
+// (gamma_l - 1) over the fluid phases. The state stores E~ = rho E - B(phi)
+// in place of rho E: for stiffened gases rho E carries the large constant
+// part B, and E~ (of the size of p) keeps the pressure inversion and the
+// energy fluxes free of cancellation in any precision. Since phi* = chi phi
+// and the unit field's star value is chi, the HLLC flux of E~ has the form of
+// that of rho E with E replaced by E~, and
+// E~_t + div((E~ + P) u) = -B(phi) div(u*) (with div(u*) the divergence of
+// the unit field's flux, the one the volume fractions use).
+template <class S>
+__device__ inline double mix_B(const Params& P, const double* phi) {
+  double b = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) b += phi[l] * P.mat[l].Bfl;
+  return b;
+}
+
+// B(phi) from the stored volume fractions of a conserved state.
+template <class S, typename T>
+__device__ inline double mix_B_cons(const Params& P, const T* U) {
+  double phi[kMaxMat], s = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) {
+    phi[l] = (double)U[S::cPHI(l)];
+    s += phi[l];
+  }
+  phi[S::N - 1] = 1.0 - s;
+  return mix_B<S>(P, phi);
 }
 
 // Mixture sound speed squared (Sec. 2.2, mass-fraction weighted over
@@ -381,8 +408,9 @@ __device__ inline void phases_w(const T* W, double* phi, double* rho) {
   for (int l = 0; l < S::N; ++l) rho[l] = (double)W[S::wRHO(l)];
 }
 
-// Conserved -> primitive (Sec. 2.2). For the elastoplastic system the
-// Hencky strain of Vbar is also returned (J2, H).
+// Conserved -> primitive (Sec. 2.2); the energy slot holds E~ = rho E -
+// B(phi). For the elastoplastic system the Hencky strain of Vbar is also
+// returned (J2, H).
 template <class S, typename T>
 __device__ inline void cons_to_prim(const Params& P, const T* U, T* W, double* Hout = nullptr,
                                     double* J2out = nullptr) {
