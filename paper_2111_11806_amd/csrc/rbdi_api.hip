@@ -423,6 +423,17 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   P.tanh_b = std::tanh(d->thinc_beta);
   P.lm_mach = d->lm_mach;
   P.solid_phase = -1;
+  {
+    double f = 1.0;
+    for (int k = 0; k < 14; ++k) {
+      if (k > 0) f *= (double)k;
+      P.exc[k] = 1.0 / f;
+    }
+    const long double ln2 = 0.6931471805599453094172321214581766L;
+    P.ln2_hi = std::ldexp(std::floor(std::ldexp((double)ln2, 32)), -32);  // k * ln2_hi exact for |k| < 2^20
+    P.ln2_lo = (double)(ln2 - (long double)P.ln2_hi);
+    P.inv_ln2 = (double)(1.0L / ln2);
+  }
 
   const size_t state_bytes = (size_t)P.fs * h->nf * h->elem;
   hipError_t e = hipSuccess;

@@ -97,10 +97,25 @@ __device__ inline void reduce_dt(DevScalars* sc, const double* __restrict__ part
 // needs dt: 1D systems).
 __global__ void k_reduce_dt(DevScalars* sc, const double* __restrict__ part, StepArgs a) { reduce_dt(sc, part, a); }
 
-template <typename T>
-__device__ inline T shup(T v) { return __shfl_up(v, 1); }
-template <typename T>
-__device__ inline T shdn(T v) { return __shfl_down(v, 1); }
+// Neighbour exchange along the wavefront by DPP whole-wave shifts (a VALU
+// move instead of an LDS permute): shup gives lane i the value of lane i-1,
+// shdn that of lane i+1; the end lanes keep their own value (they are halo
+// lanes whose results are never used).
+__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+
+__device__ inline float shup(float v) { return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, v))); }
+__device__ inline float shdn(float v) { return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, v))); }
+__device__ inline double shup(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_shr1((int)(b & 0xffffffffLL)), hi = dpp_shr1((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double shdn(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_shl1((int)(b & 0xffffffffLL)), hi = dpp_shl1((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 
 __device__ inline long long cell_index(const Params& P, int i, int j, int k) {
   return (long long)i * P.st[0] + (long long)j * P.st[1] + (long long)k * P.st[2];
@@ -383,8 +398,18 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   }
 }
 
+// Occupancy requests (waves per SIMD) of the sweep kernels: the sweeps are
+// latency-bound chains of FP64 operations, so more resident wavefronts hide
+// more of each chain.
+#ifndef RBDI_X_WAVES
+#define RBDI_X_WAVES 5
+#endif
+#ifndef RBDI_T_WAVES
+#define RBDI_T_WAVES 3
+#endif
+
 template <class S, typename T>
-__global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S::S ? 1 : RBDI_X_WAVES))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
                                                 const T* __restrict__ Dacc, T* __restrict__ Uout,
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                                 StepArgs A, double bcoef, int stage) {
@@ -404,9 +429,12 @@ __global__ __launch_bounds__(256) void k_sweep_x(Params P, const T* __restrict__
 // partials into the step's dt (this sweep itself does not use dt).
 constexpr int kRS = 65;  // LDS stride of a tile column (padded)
 
+#ifndef RBDI_TC
+#define RBDI_TC 16
+#endif
 template <class S, typename T>
 constexpr int tile_cols() {
-  return (S::NF * 16 * kRS * (int)sizeof(T) <= 48 * 1024) ? 16
+  return (S::NF * RBDI_TC * kRS * (int)sizeof(T) <= 48 * 1024) ? RBDI_TC
        : (S::NF * 8 * kRS * (int)sizeof(T) <= 48 * 1024) ? 8 : 4;
 }
 
@@ -492,7 +520,7 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
 }
 
 template <class S, typename T, int DIR, int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S::S ? 1 : RBDI_T_WAVES))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                    DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                    StepArgs A) {
   constexpr int TC = tile_cols<S, T>();

@@ -57,6 +57,8 @@ struct Params {
   int recon, riemann, seed, probe, plastic;
   double cosh_b, inv_sinh_b, tanh_b, beta;
   double lm_mach;
+  double exc[14];         // 1/k!, k = 0..13 (exponential series, kept in scalar registers)
+  double ln2_hi, ln2_lo, inv_ln2;
   int solid_phase;
   int r_static;           // rigid velocity identically zero: r never changes
   int stiff;              // some phase has a stiffening energy (B(phi) != 0)
@@ -535,6 +537,22 @@ struct Cand {
   T mL, mR, tL, tR;
 };
 
+// exp(x) in FP64 for the THINC argument: x = k ln2 + r (Cody-Waite split of
+// ln2, |r| <= ln2/2), the Taylor series of exp(r) to r^13 (truncation below
+// 5e-18), scaled by 2^k. The series coefficients come from the launch
+// parameters, i.e. scalar registers, instead of being rebuilt in vector
+// registers for every inlined call.
+__device__ inline double exp_thinc(const Params& P, double x) {
+  const double k = rint(x * P.inv_ln2);
+  double r = fma(-k, P.ln2_hi, x);
+  r = fma(-k, P.ln2_lo, r);
+  double p = P.exc[13];
+#pragma unroll
+  for (int j = 12; j >= 0; --j) p = fma(p, r, P.exc[j]);
+  return ldexp(p, (int)k);
+}
+__device__ inline float exp_thinc(const Params&, float x) { return expf(x); }
+
 template <typename T>
 __device__ inline Cand<T> candidates(const Params& P, T qm, T q0, T qp) {
   Cand<T> c;
@@ -551,7 +569,7 @@ __device__ inline Cand<T> candidates(const Params& P, T qm, T q0, T qp) {
     const T dq = fabs(qp - qm);
     const T th = qp > qm ? T(1) : T(-1);
     const T C = (q0 - qmin) * frcp(dq);
-    const T e = exp(th * T(P.beta) * (T(2) * C - T(1)));
+    const T e = exp_thinc(P, th * T(P.beta) * (T(2) * C - T(1)));
     const T tt = (T(P.cosh_b) - e) * T(P.inv_sinh_b);
     const T tb = T(P.tanh_b);
     const T hd = T(0.5) * dq;
@@ -662,6 +680,24 @@ __device__ inline void field_terms(const T* W, const SideState<S>& s, int q, int
   }
 }
 
+// sin(x) for x in [0, pi/2] by its Taylor series to x^23 in Horner form
+// (truncation below 4e-18 on the interval; no range reduction needed).
+__device__ inline double sin_quadrant(double x) {
+  const double x2 = x * x;
+  double p = -1.0 / 25852016738884976640000.0;  // -1/23!
+  p = fma(p, x2, 1.0 / 51090942171709440000.0);   // 1/21!
+  p = fma(p, x2, -1.0 / 121645100408832000.0);    // -1/19!
+  p = fma(p, x2, 1.0 / 355687428096000.0);        // 1/17!
+  p = fma(p, x2, -1.0 / 1307674368000.0);         // -1/15!
+  p = fma(p, x2, 1.0 / 6227020800.0);             // 1/13!
+  p = fma(p, x2, -1.0 / 39916800.0);              // -1/11!
+  p = fma(p, x2, 1.0 / 362880.0);                 // 1/9!
+  p = fma(p, x2, -1.0 / 5040.0);                  // -1/7!
+  p = fma(p, x2, 1.0 / 120.0);                    // 1/5!
+  p = fma(p, x2, -1.0 / 6.0);                     // -1/3!
+  return fma(p * x2, x, x);
+}
+
 // HLLC flux along DIR. Outputs the thermodynamic flux F[NT], the wall
 // velocity u* (the flux formula applied to the unit field, star value chi),
 // and the wall stretch row Vbar*_{DIR,:} (Godunov value at x/t = 0).
@@ -692,7 +728,7 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
     double ph = 1.0;
     if (P.riemann == RS_HLLC_LM && !(fabs(L.un) >= P.lm_mach * L.c || fabs(R.un) >= P.lm_mach * R.c)) {
       const double Ma = fmax(fabs(L.un) * frcp(L.c), fabs(R.un) * frcp(R.c));
-      ph = sin(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
+      ph = sin_quadrant(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
     }
     const double aS = fabs(Ss);
 #pragma unroll
