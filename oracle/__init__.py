@@ -48,7 +48,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rbdi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liborbdi.so")
 _lock = threading.Lock()
-_lib = None
+_libs = {}
 
 EOS = {"ideal": 0, "stiffened": 1, "romenskii": 2}
 BC = {"transmissive": 0, "reflective": 1, "dirichlet": 2, "periodic": 3}
@@ -58,15 +58,26 @@ SEED = {"original": 0, "riemann": 1, "none": 2}
 PROBE = {"stepout": 0, "fixed": 1}
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (plain -O2, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-shared", "-fPIC", "-o", tmp, _SRC]
+# Build variants: the reference build, and one with FMA contraction allowed
+# (-ffp-contract=fast with FMA instructions), used only to measure how far
+# rounding-order changes alone move the oracle's results (the jitter floor).
+_VARIANTS = {
+    None: ("liborbdi.so", ["-ffp-contract=off", "-fno-fast-math"]),
+    "contract": ("liborbdi_contract.so", ["-ffp-contract=fast", "-mfma", "-fno-fast-math"]),
+}
+
+
+def build(force: bool = False, variant=None) -> str:
+    """Compile the oracle with g++ (plain -O2, OpenMP, no FMA contraction
+    unless a variant asks for it)."""
+    name, flags = _VARIANTS[variant]
+    out = os.path.join(_HERE, name)
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp"] + flags + ["-shared", "-fPIC", "-o", tmp, _SRC]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 class _Desc(ctypes.Structure):
@@ -78,12 +89,10 @@ class _Desc(ctypes.Structure):
                 ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double)]
 
 
-def lib():
-    global _lib
+def lib(variant=None):
     with _lock:
-        if _lib is None:
-            build()
-            L = ctypes.CDLL(_LIB)
+        if variant not in _libs:
+            L = ctypes.CDLL(build(variant=variant))
             vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
             L.orc_create.restype = vp
             L.orc_create.argtypes = [ctypes.POINTER(_Desc)]
@@ -116,8 +125,8 @@ def lib():
             L.orc_solid_sources.argtypes = [vp, dp]
             L.orc_hencky.argtypes = [dp, dp]
             L.orc_phase_ref.argtypes = [ip, dp, ctypes.c_double, ctypes.c_double, dp]
-            _lib = L
-    return _lib
+            _libs[variant] = L
+    return _libs[variant]
 
 
 def _dp(a):
@@ -143,8 +152,9 @@ def material_params(m) -> np.ndarray:
 class Oracle:
     """One oracle instance of a :class:`paper_2111_11806_amd.inputs.Problem`."""
 
-    def __init__(self, prob):
-        L = lib()
+    def __init__(self, prob, variant=None):
+        L = lib(variant)
+        self._L = L
         d = _Desc()
         d.dim = prob.dim
         d.nx, d.ny, d.nz = prob.n
@@ -179,7 +189,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     @property
@@ -188,62 +198,62 @@ class Oracle:
         return (self.nf, nz, ny, nx)
 
     def set_state_prim(self, W):
-        lib().orc_set_state_prim(self._h, _dp(_arr(W, int(np.prod(self.shape)))))
+        self._L.orc_set_state_prim(self._h, _dp(_arr(W, int(np.prod(self.shape)))))
 
     def set_state_cons(self, U):
-        lib().orc_set_state_cons(self._h, _dp(_arr(U, int(np.prod(self.shape)))))
+        self._L.orc_set_state_cons(self._h, _dp(_arr(U, int(np.prod(self.shape)))))
 
     def get_state_prim(self):
         out = np.empty(self.shape)
-        lib().orc_get_state_prim(self._h, _dp(out))
+        self._L.orc_get_state_prim(self._h, _dp(out))
         return out
 
     def get_state_cons(self):
         out = np.empty(self.shape)
-        lib().orc_get_state_cons(self._h, _dp(out))
+        self._L.orc_get_state_cons(self._h, _dp(out))
         return out
 
     def set_rigid_sdf(self, sdf, width, v, omega, center):
         sdf = _arr(sdf, int(np.prod(self.shape[1:])))
-        lib().orc_set_rigid_sdf(self._h, _dp(sdf), float(width), _dp(_arr(v, 3)), _dp(_arr(omega, 3)),
+        self._L.orc_set_rigid_sdf(self._h, _dp(sdf), float(width), _dp(_arr(v, 3)), _dp(_arr(omega, 3)),
                                 _dp(_arr(center, 3)))
 
     def set_rigid_motion(self, v, omega, center):
-        lib().orc_set_rigid_motion(self._h, _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3)))
+        self._L.orc_set_rigid_motion(self._h, _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3)))
 
     def compute_dt(self, cfl):
-        return lib().orc_compute_dt(self._h, float(cfl))
+        return self._L.orc_compute_dt(self._h, float(cfl))
 
     def step(self, dt):
-        lib().orc_step(self._h, float(dt))
+        self._L.orc_step(self._h, float(dt))
 
     def seed(self):
-        lib().orc_seed(self._h)
+        self._L.orc_seed(self._h)
 
     def rhs(self, dirmask=7):
         """D(U) of the current state (no seeding; rigid mask from r)."""
         out = np.empty(self.shape)
-        lib().orc_rhs(self._h, _dp(out), int(dirmask))
+        self._L.orc_rhs(self._h, _dp(out), int(dirmask))
         return out
 
     @property
     def t(self):
-        return lib().orc_time(self._h)
+        return self._L.orc_time(self._h)
 
     def stats(self):
         out = (ctypes.c_long * 3)()
-        lib().orc_stats(self._h, out)
+        self._L.orc_stats(self._h, out)
         return {"seeded": out[0], "probe_fail": out[1], "fallback": out[2]}
 
     def rigid_force(self, center):
         F = np.zeros(3)
         T = np.zeros(3)
-        lib().orc_rigid_force(self._h, _dp(_arr(center, 3)), _dp(F), _dp(T))
+        self._L.orc_rigid_force(self._h, _dp(_arr(center, 3)), _dp(F), _dp(T))
         return F, T
 
     def conserved_totals(self):
         out = np.zeros(2 * self.nf)
-        lib().orc_conserved_totals(self._h, _dp(out))
+        self._L.orc_conserved_totals(self._h, _dp(out))
         return out[: self.nf], out[self.nf:]
 
     def run(self, t_end=None, cfl=None, nsteps=None, dts=None):
@@ -267,50 +277,50 @@ class Oracle:
     # ---- unit-level access used by the pins ----
     def candidates(self, qm, q0, qp):
         out = np.zeros(4)
-        lib().orc_candidates(self._h, qm, q0, qp, _dp(out))
+        self._L.orc_candidates(self._h, qm, q0, qp, _dp(out))
         return out
 
     def prim_to_cons(self, W):
         U = np.zeros(self.nf)
-        lib().orc_prim_to_cons(self._h, _dp(_arr(W, self.nf)), _dp(U))
+        self._L.orc_prim_to_cons(self._h, _dp(_arr(W, self.nf)), _dp(U))
         return U
 
     def cons_to_prim(self, U):
         W = np.zeros(self.nf)
-        lib().orc_cons_to_prim(self._h, _dp(_arr(U, self.nf)), _dp(W))
+        self._L.orc_cons_to_prim(self._h, _dp(_arr(U, self.nf)), _dp(W))
         return W
 
     def thermo(self, W):
         out = np.zeros(24)
-        lib().orc_thermo(self._h, _dp(_arr(W, self.nf)), _dp(out))
+        self._L.orc_thermo(self._h, _dp(_arr(W, self.nf)), _dp(out))
         return {"rho": out[0], "p": out[1], "c2": out[2], "G": out[3], "sigY": out[4], "J2": out[5],
                 "sigma": out[6:15].reshape(3, 3), "H": out[15:24].reshape(3, 3)}
 
     def face_flux(self, WL, WR, d):
         out = np.zeros(self.nf + 3)
-        lib().orc_face_flux(self._h, _dp(_arr(WL, self.nf)), _dp(_arr(WR, self.nf)), int(d), _dp(out))
+        self._L.orc_face_flux(self._h, _dp(_arr(WL, self.nf)), _dp(_arr(WR, self.nf)), int(d), _dp(out))
         nt = self.nf - 1
         return out[:nt], out[nt], out[nt + 1: nt + 4]
 
     def phys_flux(self, W, d):
         F = np.zeros(self.nf)
-        lib().orc_phys_flux(self._h, _dp(_arr(W, self.nf)), int(d), _dp(F))
+        self._L.orc_phys_flux(self._h, _dp(_arr(W, self.nf)), int(d), _dp(F))
         return F[: self.nf - 1]
 
     def mirror_state(self, W, nrm, v):
         out = np.zeros(self.nf)
-        lib().orc_mirror_state(self._h, _dp(_arr(W, self.nf)), _dp(_arr(nrm, 3)), _dp(_arr(v, 3)), _dp(out))
+        self._L.orc_mirror_state(self._h, _dp(_arr(W, self.nf)), _dp(_arr(nrm, 3)), _dp(_arr(v, 3)), _dp(out))
         return out
 
     def riemann_seed_state(self, Wm, Wi, nrm):
         out = np.zeros(self.nf)
-        lib().orc_riemann_seed_state(self._h, _dp(_arr(Wm, self.nf)), _dp(_arr(Wi, self.nf)),
+        self._L.orc_riemann_seed_state(self._h, _dp(_arr(Wm, self.nf)), _dp(_arr(Wi, self.nf)),
                                      _dp(_arr(nrm, 3)), _dp(out))
         return out
 
     def solid_sources(self, U):
         U = _arr(U, self.nf).copy()
-        lib().orc_solid_sources(self._h, _dp(U))
+        self._L.orc_solid_sources(self._h, _dp(U))
         return U
 
 

@@ -285,3 +285,19 @@ def test_copper_indenter_3d_reduced(rbdi):
     prob = inputs.copper_indenter(24)
     orc, gpu, _ = _pair(rbdi, prob, nsteps=8)
     _check(orc, gpu, TOL64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_run_to_run_bitwise(rbdi, precision):
+    """Determinism: the same problem advanced twice (device CFL steps, fixed-
+    order reductions, no atomics on results) gives identical bits."""
+    for prob, n in ((inputs.shock_cylinder(160, 80), 60), (inputs.copper_indenter(20), 6)):
+        out = []
+        for _ in range(2):
+            s = rbdi.Solver(prob, precision)
+            s.advance(prob.cfl, n, prob.t_end)
+            F, T = s.rigid_force(prob.center)
+            out.append((s.get_state_cons(), F, T, s.status()["t"]))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+        assert out[0][3] == out[1][3]

@@ -660,3 +660,22 @@ def test_indenter_keeps_mirror_symmetry():
             scale = max(np.abs(U[q]).max(), 1e-300)
             assert np.abs(U[q] - m).max() <= 1e-9 * scale + 1e-12, (axis, nm)
     assert o.stats()["fallback"] > 0
+
+
+def test_oracle_jitter_floor():
+    """How far a change of rounding order alone (FMA contraction allowed)
+    moves the oracle after 80 steps of the 160 x 80 shock/cylinder problem:
+    the floor under which parity differences carry no information. It must
+    sit well below the 1e-10 bar of the FP64 parity tests."""
+    import oracle as orc_mod
+    prob = inputs.shock_cylinder(160, 80)
+    a = orc_mod.Oracle(prob)
+    dts = a.run(nsteps=80)
+    b = orc_mod.Oracle(prob, variant="contract")
+    b.run(dts=dts)
+    ua, ub = a.get_state_cons(), b.get_state_cons()
+    num = np.abs(ua - ub).reshape(ua.shape[0], -1).sum(1)
+    den = np.abs(ua).reshape(ua.shape[0], -1).sum(1)
+    rel = num / np.where(den > 0, den, 1.0)
+    print("oracle jitter floor (rel L1 per field, contract vs off):", rel)
+    assert np.all(rel < 1e-11)
