@@ -679,3 +679,18 @@ def test_oracle_jitter_floor():
     rel = num / np.where(den > 0, den, 1.0)
     print("oracle jitter floor (rel L1 per field, contract vs off):", rel)
     assert np.all(rel < 1e-11)
+
+
+def test_shock_cylinder_mirror_symmetry():
+    """The shock/cylinder problem is symmetric about y = 0.25 (the cylinder
+    axis, the middle of the grid): after 60 steps every field is even in y
+    except the y momentum, which is odd, to roundoff."""
+    p = inputs.shock_cylinder(160, 80)
+    o = oracle.Oracle(p)
+    o.run(nsteps=60)
+    U = o.get_state_cons()
+    for q, nm in enumerate(p.cons_names()):
+        m = np.flip(U[q], axis=1) * (-1.0 if nm == "my" else 1.0)
+        scale = max(np.abs(U[q]).max(), 1e-300)
+        assert np.abs(U[q] - m).max() <= 1e-11 * scale, nm
+    assert np.abs(U[p.cons_names().index("my")]).max() > 1e-3  # the flow is not trivially y-free
