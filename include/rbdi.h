@@ -56,7 +56,7 @@ typedef enum {
   RBDI_ERR_HIP = -3,         /* a HIP runtime call failed */
   RBDI_ERR_NONPHYSICAL = -4, /* a cell left the admissible set (rbdi_status) */
   RBDI_ERR_NOT_READY = -5,   /* call order violated (e.g. step before state) */
-  RBDI_ERR_UNSUPPORTED = -6  /* this build has no kernel for the combination */
+  RBDI_ERR_UNSUPPORTED = -6  /* the library has no kernel for the combination */
 } rbdi_error;
 
 enum { RBDI_EOS_IDEAL = 0, RBDI_EOS_STIFFENED = 1, RBDI_EOS_ROMENSKII = 2 };
