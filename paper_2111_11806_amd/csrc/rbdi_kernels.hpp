@@ -398,18 +398,19 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   }
 }
 
-// Occupancy requests (waves per SIMD) of the sweep kernels: the sweeps are
-// latency-bound chains of FP64 operations, so more resident wavefronts hide
-// more of each chain.
-#ifndef RBDI_X_WAVES
-#define RBDI_X_WAVES 5
-#endif
-#ifndef RBDI_T_WAVES
-#define RBDI_T_WAVES 3
-#endif
+// Occupancy requests (waves per SIMD) of the single-gas sweep kernels: the
+// sweeps are latency-bound chains of FP64 operations, so more resident
+// wavefronts hide more of each chain, as long as the register budget does
+// not force spills (measured: five for the 2D x sweep; the LDS tile holds
+// the y/z sweeps at three). Other systems: the compiler's choice (1 = no
+// request).
+template <class S>
+constexpr int x_sweep_waves() { return (S::S || S::N != 1) ? 1 : (S::D == 2 ? 5 : 4); }
+template <class S>
+constexpr int tile_sweep_waves() { return (S::S || S::N != 1) ? 1 : 3; }
 
 template <class S, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S::S ? 1 : RBDI_X_WAVES))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
                                                 const T* __restrict__ Dacc, T* __restrict__ Uout,
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                                 StepArgs A, double bcoef, int stage) {
@@ -520,7 +521,7 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
 }
 
 template <class S, typename T, int DIR, int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S::S ? 1 : RBDI_T_WAVES))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tile_sweep_waves<S>()))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                    DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                    StepArgs A) {
   constexpr int TC = tile_cols<S, T>();

@@ -698,6 +698,29 @@ __device__ inline double sin_quadrant(double x) {
   return fma(p * x2, x, x);
 }
 
+// Toro's HLLC flux from side K (the side whose fan region holds x/t = 0):
+// F = F_K, or with star = true F_K + S_K (U*_K - U_K).
+template <class S, int DIR, typename T>
+__device__ inline void toro_side(const T* WK, const SideState<S>& K, int sp, double Sk, double Ss, bool star, T* F,
+                                 T& ustar, T* Vstar) {
+  const double chi = star ? (Sk - K.un) * frcp(Sk - Ss) : 1.0;
+  double cn = 1.0, ct = 1.0;
+  if constexpr (S::S) {
+    if (star) { ct = cbrt(chi); cn = 1.0 / (ct * ct); }
+  }
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) {
+    double u, f, us;
+    field_terms<S, DIR>(WK, K, q, sp, Sk, Ss, chi, cn, ct, u, f, us);
+    F[q] = (T)(star ? f + Sk * (us - u) : f);
+  }
+  ustar = (T)(star ? K.un + Sk * (chi - 1.0) : K.un);
+  if constexpr (S::S) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Vstar[b] = (T)((double)WK[S::wV(DIR, b)] * (star ? cn : 1.0));
+  }
+}
+
 // HLLC flux along DIR. Outputs the thermodynamic flux F[NT], the wall
 // velocity u* (the flux formula applied to the unit field, star value chi),
 // and the wall stretch row Vbar*_{DIR,:} (Godunov value at x/t = 0).
@@ -750,31 +773,11 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
     }
     return;
   }
-  // Toro HLLC: pick the side K whose fan region contains x/t = 0.
-  bool useL, star;
-  if (SL >= 0.0) { useL = true; star = false; }
-  else if (Ss >= 0.0) { useL = true; star = true; }
-  else if (SR > 0.0) { useL = false; star = true; }
-  else { useL = false; star = false; }
-  const SideState<S>& K = useL ? L : R;
-  const T* WK = useL ? WL : WR;
-  const double Sk = useL ? SL : SR;
-  const double chi = star ? (Sk - K.un) * frcp(Sk - Ss) : 1.0;
-  double cn = 1.0, ct = 1.0;
-  if constexpr (S::S) {
-    if (star) { ct = cbrt(chi); cn = 1.0 / (ct * ct); }
-  }
-#pragma unroll
-  for (int q = 0; q < S::NT; ++q) {
-    double u, f, us;
-    field_terms<S, DIR>(WK, K, q, sp, Sk, Ss, chi, cn, ct, u, f, us);
-    F[q] = (T)(star ? f + Sk * (us - u) : f);
-  }
-  ustar = (T)(star ? K.un + Sk * (chi - 1.0) : K.un);
-  if constexpr (S::S) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b) Vstar[b] = (T)((double)WK[S::wV(DIR, b)] * (star ? cn : 1.0));
-  }
+  // Toro HLLC: the side K whose fan region contains x/t = 0 (both sides are
+  // spelled out, so that no array or state is selected by reference at run
+  // time: such a selection would place them in scratch memory).
+  if (SL >= 0.0 || Ss >= 0.0) toro_side<S, DIR>(WL, L, sp, SL, Ss, !(SL >= 0.0), F, ustar, Vstar);
+  else toro_side<S, DIR>(WR, R, sp, SR, Ss, SR > 0.0, F, ustar, Vstar);
 }
 
 // ---------------------------------------------------------------------------
