@@ -26,6 +26,10 @@ What pins each part of the oracle (tests marked ``not gpu``):
   conservation to 1e-12 with periodic boundaries.
 * Seeding (Sec. 3.2): Householder reflection identities, equality with an
   explicit rotate-reflect-rotate-back, the Riemann variant's S* = v_r.n.
+* ELVIRA normal (Sec. 3.3): cut fractions against the closed-form area
+  below a line, exact reproduction of straight interfaces (and the seeded
+  mirror state of a sharp ramp), convergence on a circle with exact cell
+  areas, block symmetries.
 * Force (O.6 reading): summation-by-parts identity, uniform and linear
   pressure fields.
 * Elastoplastic closure: Hencky strain of diagonal and rotated stretches,
@@ -56,6 +60,7 @@ RECON = {"muscl": 0, "bvd_thinc": 1}
 RIEMANN = {"hllc": 0, "hllc_lm": 1}
 SEED = {"original": 0, "riemann": 1, "none": 2}
 PROBE = {"stepout": 0, "fixed": 1}
+NORMAL = {"youngs": 0, "elvira": 1}
 
 
 # Build variants: the reference build, and one with FMA contraction allowed
@@ -86,7 +91,7 @@ class _Desc(ctypes.Structure):
                 ("nmat", ctypes.c_int), ("solid", ctypes.c_int), ("bc", ctypes.c_int * 6),
                 ("recon", ctypes.c_int), ("riemann", ctypes.c_int), ("seed", ctypes.c_int),
                 ("probe", ctypes.c_int), ("plastic", ctypes.c_int),
-                ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double)]
+                ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double), ("normal", ctypes.c_int)]
 
 
 def lib(variant=None):
@@ -125,6 +130,10 @@ def lib(variant=None):
             L.orc_solid_sources.argtypes = [vp, dp]
             L.orc_hencky.argtypes = [dp, dp]
             L.orc_phase_ref.argtypes = [ip, dp, ctypes.c_double, ctypes.c_double, dp]
+            L.orc_elvira_normal.restype = ip
+            L.orc_elvira_normal.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+            L.orc_cut_fraction.restype = ctypes.c_double
+            L.orc_cut_fraction.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
             _libs[variant] = L
     return _libs[variant]
 
@@ -172,6 +181,7 @@ class Oracle:
         d.plastic = int(prob.plastic)
         d.thinc_beta = prob.thinc_beta
         d.lm_mach = prob.lm_mach
+        d.normal = NORMAL[prob.normal]
         self._h = L.orc_create(ctypes.byref(d))
         if not self._h:
             raise RuntimeError("orc_create failed")

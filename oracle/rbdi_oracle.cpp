@@ -37,6 +37,7 @@ enum { REC_MUSCL = 0, REC_BVD_THINC = 1 };
 enum { RS_HLLC = 0, RS_HLLC_LM = 1 };
 enum { SEED_ORIGINAL = 0, SEED_RIEMANN = 1, SEED_NONE = 2 };
 enum { PROBE_STEPOUT = 0, PROBE_FIXED = 1 };
+enum { NORMAL_YOUNGS = 0, NORMAL_ELVIRA = 1 };
 
 struct Material {
   int kind = EOS_IDEAL;
@@ -236,6 +237,7 @@ struct Oracle {
   int bc[6] = {0, 0, 0, 0, 0, 0};
   std::vector<double> bcU[6];
   int recon = REC_BVD_THINC, riemann = RS_HLLC, seed = SEED_ORIGINAL, probe = PROBE_STEPOUT;
+  int normal = NORMAL_YOUNGS;
   int plastic = 1;
   double beta_thinc = 1.6;
   double lm_mach = 0.1;
@@ -814,11 +816,120 @@ struct Oracle {
     for (int q = 0; q < 9; ++q) Uc[L.V(0, 0) + q] = V[q / 3][q % 3];
   }
 
+  // ---- ELVIRA normal (Sec. 3.3; Pilliod and Puckett's second-order method) --
+
+  // Fraction of the cell [-hx/2,hx/2] x [-hy/2,hy/2] on the side n.p <= beta
+  // of a straight line: the cell rectangle is clipped by the half-plane and
+  // the area of the clipped polygon is taken by the shoelace formula.
+  static double cut_fraction(const double nv[2], double hx, double hy, double beta) {
+    const double px[4] = {-0.5 * hx, 0.5 * hx, 0.5 * hx, -0.5 * hx};
+    const double py[4] = {-0.5 * hy, -0.5 * hy, 0.5 * hy, 0.5 * hy};
+    double qx[8], qy[8];
+    int m = 0;
+    for (int e = 0; e < 4; ++e) {
+      const int f = (e + 1) % 4;
+      const double se = nv[0] * px[e] + nv[1] * py[e] - beta;
+      const double sf = nv[0] * px[f] + nv[1] * py[f] - beta;
+      if (se <= 0.0) { qx[m] = px[e]; qy[m] = py[e]; ++m; }
+      if ((se < 0.0 && sf > 0.0) || (se > 0.0 && sf < 0.0)) {
+        const double t = se / (se - sf);
+        qx[m] = px[e] + t * (px[f] - px[e]);
+        qy[m] = py[e] + t * (py[f] - py[e]);
+        ++m;
+      }
+    }
+    double a2 = 0.0;
+    for (int e = 0; e < m; ++e) {
+      const int f = (e + 1) % m;
+      a2 += qx[e] * qy[f] - qx[f] * qy[e];
+    }
+    return 0.5 * std::fabs(a2) / (hx * hy);
+  }
+
+  // The line offset beta whose cut fraction is frac (0 < frac < 1), by
+  // bisection on the nondecreasing cut_fraction.
+  static double cut_offset(const double nv[2], double hx, double hy, double frac) {
+    double hi = 0.5 * (std::fabs(nv[0]) * hx + std::fabs(nv[1]) * hy), lo = -hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      if (cut_fraction(nv, hx, hy, mid) < frac) lo = mid;
+      else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  }
+
+  // ELVIRA on the 3x3 block f[a+1][b+1] = r(i+a, j+b) of a rigid cell.
+  // Candidate lines: the interface as a graph over x, with slopes from the
+  // backward, central and forward differences of the column sums, and as a
+  // graph over y from the row sums. Readings: the body lies on the side of
+  // each family given by the sign of the opposite block sums (the bottom vs
+  // top rows for graphs over x, the left vs right columns for graphs over
+  // y); a family whose sign is zero is left out. Each candidate line is
+  // placed so that it cuts the centre cell at its own fraction, and the one
+  // whose fractions in the nine cells differ least from f in the sum of
+  // squares wins (first in the order above on ties). The outward normal
+  // points away from the body. Returns false when f(centre) is not strictly
+  // between 0 and 1 or no family is defined.
+  static bool elvira_normal(const double f[3][3], double hx, double hy, double nout[2]) {
+    const double fc = f[1][1];
+    if (!(fc > 0.0 && fc < 1.0)) return false;
+    double H[3], Wr[3];
+    for (int a = 0; a < 3; ++a) H[a] = hy * (f[a][0] + f[a][1] + f[a][2]);
+    for (int b = 0; b < 3; ++b) Wr[b] = hx * (f[0][b] + f[1][b] + f[2][b]);
+    const double sy = Wr[2] > Wr[0] ? 1.0 : (Wr[2] < Wr[0] ? -1.0 : 0.0);
+    const double sx = H[2] > H[0] ? 1.0 : (H[2] < H[0] ? -1.0 : 0.0);
+    double cand[6][2];
+    int nc = 0;
+    if (sy != 0.0) {
+      const double sl[3] = {(H[1] - H[0]) / hx, (H[2] - H[0]) / (2.0 * hx), (H[2] - H[1]) / hx};
+      for (int c = 0; c < 3; ++c) { cand[nc][0] = -sl[c]; cand[nc][1] = -sy; ++nc; }
+    }
+    if (sx != 0.0) {
+      const double sl[3] = {(Wr[1] - Wr[0]) / hy, (Wr[2] - Wr[0]) / (2.0 * hy), (Wr[2] - Wr[1]) / hy};
+      for (int c = 0; c < 3; ++c) { cand[nc][0] = -sx; cand[nc][1] = -sl[c]; ++nc; }
+    }
+    if (nc == 0) return false;
+    double best = 0.0;
+    int ib = -1;
+    for (int c = 0; c < nc; ++c) {
+      const double mag = std::sqrt(cand[c][0] * cand[c][0] + cand[c][1] * cand[c][1]);
+      const double nv[2] = {cand[c][0] / mag, cand[c][1] / mag};
+      const double beta = cut_offset(nv, hx, hy, fc);
+      double err = 0.0;
+      for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b) {
+          const double e = cut_fraction(nv, hx, hy, beta - nv[0] * a * hx - nv[1] * b * hy) - f[a + 1][b + 1];
+          err += e * e;
+        }
+      if (ib < 0 || err < best) { best = err; ib = c; nout[0] = nv[0]; nout[1] = nv[1]; }
+    }
+    return true;
+  }
+
   // ---- rigid-body interface seeding (Sec. 3.2, the seeding routine) --------
+
+  // Normal of the rigid cell (i,j,k) (Sec. 3.3): ELVIRA in 2D when selected
+  // and defined (a fraction strictly between 0 and 1 and at least one
+  // candidate family), otherwise Youngs. Ghost values come from the filled
+  // ghost layers (corners included).
+  bool normal_at(const std::vector<double>& X, int i, int j, int k, double nrm[3]) const {
+    const double* r = X.data() + (size_t)L.R() * ncell;
+    if (normal == NORMAL_ELVIRA && dim == 2) {
+      double f[3][3], n2[2];
+      for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b) f[a + 1][b + 1] = r[idx(i + a, j + b, k)];
+      if (elvira_normal(f, dx[0], dx[1], n2)) {
+        nrm[0] = n2[0]; nrm[1] = n2[1]; nrm[2] = 0.0;
+        return true;
+      }
+    }
+    return youngs_at(X, i, j, k, nrm);
+  }
 
   // Youngs normal (Sec. 3.3): n = -grad r / |grad r| with central
   // differences. Returns false where the gradient vanishes.
-  bool normal_at(const std::vector<double>& X, int i, int j, int k, double nrm[3]) const {
+  bool youngs_at(const std::vector<double>& X, int i, int j, int k, double nrm[3]) const {
     const double* r = X.data() + (size_t)L.R() * ncell;
     const size_t c = idx(i, j, k);
     double gr[3] = {0, 0, 0}, mag = 0;
@@ -911,7 +1022,7 @@ struct Oracle {
 
   // Seeding (Sec. 3.2), once per time step before the hyperbolic update, on
   // every rigid cell (r > 0.5):
-  //  1. outward normal n (Youngs);
+  //  1. outward normal n (Youngs, or ELVIRA in 2D);
   //  2. probe along n. Reading: step-out distances 1, 1.5, ..., 4 dx (or the
   //     fixed 1.5 dx probe); a probe point is valid when every enclosing cell
   //     centre that carries a nonzero interpolation weight is an interior cell
@@ -1117,6 +1228,7 @@ struct orc_desc {
   int bc[6];
   int recon, riemann, seed, probe, plastic;
   double thinc_beta, lm_mach;
+  int normal;
 };
 
 ORC_API const char* orc_last_error() { return g_err.c_str(); }
@@ -1138,6 +1250,7 @@ ORC_API void* orc_create(const orc_desc* d) {
   o->recon = d->recon; o->riemann = d->riemann; o->seed = d->seed; o->probe = d->probe;
   o->plastic = d->plastic;
   o->beta_thinc = d->thinc_beta; o->lm_mach = d->lm_mach;
+  o->normal = d->normal;
   o->ncell = (size_t)o->N[0] * o->N[1] * o->N[2];
   o->U.assign((size_t)o->L.n * o->ncell, 0.0);
   return o;
@@ -1415,6 +1528,17 @@ ORC_API void orc_mirror_state(void* h, const double* W, const double* nrm, const
 
 ORC_API void orc_riemann_seed_state(void* h, const double* Wm, const double* Wi, const double* nrm, double* Wout) {
   static_cast<Oracle*>(h)->riemann_star_right(Wm, Wi, nrm, Wout);
+}
+
+// ELVIRA pieces for the pins: normal of a 3x3 block f9[(a+1)*3 + (b+1)] =
+// r(i+a, j+b) (returns 0 where undefined), and the cut fraction of a cell.
+ORC_API int orc_elvira_normal(const double* f9, double hx, double hy, double* n2) {
+  double f[3][3];
+  for (int q = 0; q < 9; ++q) f[q / 3][q % 3] = f9[q];
+  return Oracle::elvira_normal(f, hx, hy, n2) ? 1 : 0;
+}
+ORC_API double orc_cut_fraction(const double* n2, double hx, double hy, double beta) {
+  return Oracle::cut_fraction(n2, hx, hy, beta);
 }
 
 ORC_API void orc_solid_sources(void* h, double* Uc) { static_cast<Oracle*>(h)->solid_sources(Uc); }

@@ -19,6 +19,9 @@ Workloads (sizes and states as the method's own test problems prescribe):
 * ``copper_indenter`` 3D copper (Romenskii, perfect plasticity) in air with a
                       flat-ended rigid cylinder pressed in at 200 m/s.
 * ``batch``           64 seeded 2D shock/rigid-ellipse instances.
+* ``wedge``           2D planar shock reflecting from a static rigid wedge
+                      (Mach 1.7 / 25 degrees, or Mach 10 / 30 degrees),
+                      ELVIRA normals.
 """
 from __future__ import annotations
 
@@ -50,6 +53,7 @@ class Problem:
     riemann: str = "hllc"
     seed: str = "original"
     probe: str = "stepout"
+    normal: str = "youngs"        # rigid-body normal: "youngs" or "elvira" (2D)
     plastic: bool = True
     thinc_beta: float = 1.6
     lm_mach: float = 0.1
@@ -181,6 +185,34 @@ def shock_cylinder(nx=1024, ny=512, mach=2.8, riemann="hllc_lm", recon="bvd_thin
                    bc=["dirichlet", "transmissive", "reflective", "reflective", "transmissive", "transmissive"],
                    bc_states={0: inflow}, W0=W, sdf=sdf, width=1.0, recon=recon, riemann=riemann,
                    cfl=0.4, t_end=0.3)
+
+
+def wedge(nx=1200, ny=800, mach=1.7, angle_deg=25.0, x_wedge=0.5, x_shock=0.25, normal="elvira",
+          recon="bvd_thinc", riemann="hllc"):
+    """2D planar shock (gamma 1.4; quiescent rho = 1.4, p = 1) on [0,3] x
+    [0,2] reflecting from a static rigid wedge: the region below the line
+    through (x_wedge, 0) at angle_deg to the x axis. The default grid is the
+    finest level of a 300 x 200 base grid with two refinements by 2, as a
+    uniform grid. Mach 1.7 / 25 degrees runs to t = 1.2, Mach 10 / 30
+    degrees to t = 0.2."""
+    dx = 3.0 / nx
+    dy = 2.0 / ny
+    X, Y, _ = _mesh((nx, ny, 1), (dx, dy, 1.0), (0.0, 0.0, 0.0))
+    rho2, u2, p2 = normal_shock_state(mach, 1.4, 1.4, 1.0)
+    post = X < x_shock
+    W = np.zeros((5, 1, ny, nx))
+    W[0] = np.where(post, rho2, 1.4)
+    W[1] = np.where(post, u2, 0.0)
+    W[2] = 0.0
+    W[3] = np.where(post, p2, 1.0)
+    th = math.radians(angle_deg)
+    sdf = math.cos(th) * Y - math.sin(th) * (X - x_wedge)   # distance to the ramp line
+    inflow = np.array([rho2, u2, 0.0, p2, 0.0])
+    return Problem(name="wedge", dim=2, n=(nx, ny, 1), dx=(dx, dy, 1.0), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False,
+                   bc=["dirichlet", "transmissive", "reflective", "transmissive", "transmissive", "transmissive"],
+                   bc_states={0: inflow}, W0=W, sdf=sdf, width=1.0, recon=recon, riemann=riemann,
+                   normal=normal, cfl=0.4, t_end=1.2 if mach < 5 else 0.2)
 
 
 def air_water(nx=2048, ny=1024, eps=1e-6):
