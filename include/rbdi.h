@@ -65,6 +65,7 @@ enum { RBDI_RECON_MUSCL = 0, RBDI_RECON_BVD_THINC = 1 };
 enum { RBDI_RIEMANN_HLLC = 0, RBDI_RIEMANN_HLLC_LM = 1 };
 enum { RBDI_SEED_ORIGINAL = 0, RBDI_SEED_RIEMANN = 1, RBDI_SEED_NONE = 2 };
 enum { RBDI_PROBE_STEPOUT = 0, RBDI_PROBE_FIXED = 1 };
+enum { RBDI_NORMAL_YOUNGS = 0, RBDI_NORMAL_ELVIRA = 1 };
 enum { RBDI_FP64 = 0, RBDI_FP32 = 1 };
 
 /* Grid, system and scheme of one instance.
@@ -77,7 +78,13 @@ enum { RBDI_FP64 = 0, RBDI_FP32 = 1 };
  * probe: RBDI_PROBE_*; plastic: apply the plastic return (solid only);
  * thinc_beta: THINC steepness; lm_mach: HLLC-LM Mach limit;
  * precision: RBDI_FP64, or RBDI_FP32 (flux and reconstruction in FP32; the
- * mixture-pressure inversion, dt, force/torque and totals in FP64). */
+ * mixture-pressure inversion, dt, force/torque and totals in FP64).
+ * normal: RBDI_NORMAL_* (Sec. 3.3), the rigid-body normal used by seeding:
+ * Youngs' central differences, or ELVIRA (dim = 2 only; BAD_ARG otherwise):
+ * the best of six candidate lines from backward/central/forward differences
+ * of the 3x3 column and row sums of r, judged by the volume fractions each
+ * line gives the nine cells; Youngs where the centre fraction is 0 or 1 or
+ * no candidate exists. Always computed in FP64. */
 typedef struct {
   int dim;
   int n[3];
@@ -94,6 +101,7 @@ typedef struct {
   double thinc_beta;
   double lm_mach;
   int precision;
+  int normal;
 } rbdi_desc;
 
 /* Equation of state of one material (Sec. 2.1.3 and the Mie-Gruneisen form of

@@ -382,8 +382,9 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
       return fail(RBDI_ERR_BAD_ARG, "periodic boundaries must be paired");
   }
   if (d->recon < 0 || d->recon > 1 || d->riemann < 0 || d->riemann > 1 || d->seed < 0 || d->seed > 2 ||
-      d->probe < 0 || d->probe > 1)
+      d->probe < 0 || d->probe > 1 || d->normal < 0 || d->normal > 1)
     return fail(RBDI_ERR_BAD_ARG, "bad scheme option");
+  if (d->normal == RBDI_NORMAL_ELVIRA && d->dim != 2) return fail(RBDI_ERR_BAD_ARG, "ELVIRA normals are 2D only");
   if (d->recon == RBDI_RECON_BVD_THINC && !(d->thinc_beta > 0.0)) return fail(RBDI_ERR_BAD_ARG, "thinc_beta must be > 0");
   if (d->riemann == RBDI_RIEMANN_HLLC_LM && !(d->lm_mach > 0.0)) return fail(RBDI_ERR_BAD_ARG, "lm_mach must be > 0");
   const Ops* ops = d->precision == RBDI_FP64 ? pick<double>(d->dim, d->nmat, d->solid)
@@ -416,6 +417,7 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   P.riemann = d->riemann;
   P.seed = d->seed;
   P.probe = d->probe;
+  P.normal = d->normal;
   P.plastic = d->plastic;
   P.beta = d->thinc_beta;
   P.cosh_b = std::cosh(d->thinc_beta);

@@ -556,7 +556,119 @@ __device__ inline bool youngs_normal(const Params& P, const T* __restrict__ U, i
   return true;
 }
 
-// Seeding geometry of one rigid cell (Sec. 3.2 steps 1-2): Youngs normal,
+// ELVIRA (Sec. 3.3, after Pilliod and Puckett), 2D.
+//
+// r at (i+a, j+b) for |a|, |b| <= 1 with ghost positions mapped as the
+// domain ghost layers are filled: along y first (a Dirichlet face gives its
+// state), then along x within the source row.
+template <class S, typename T>
+__device__ inline double r_block(const Params& P, const T* __restrict__ U, int i, int j, int k) {
+  int sj, sx, face;
+  const int my = ghost_map(P, 1, j, sj, face);
+  if (my == 2) return P.bcW[face][S::R];
+  const int mx = ghost_map(P, 0, i, sx, face);
+  if (mx == 2) return P.bcW[face][S::R];
+  return (double)U[S::R * P.fs + cell_index(P, sx, sj, k)];
+}
+
+// Fraction of a cell of sides hx, hy lying on the side n.p <= beta of the
+// line with unit normal n (p measured from the cell centre): with
+// c1 <= c2 the two projections |n_x| hx, |n_y| hy and s = beta + (c1+c2)/2
+// the distance from the lowest corner, the cut is a triangle (s < c1), a
+// trapezoid (s <= c2) or the complement of a triangle.
+__device__ inline double cut_fraction(double nx, double ny, double hx, double hy, double beta) {
+  double c1 = fabs(nx) * hx, c2 = fabs(ny) * hy;
+  if (c1 > c2) { const double t = c1; c1 = c2; c2 = t; }
+  const double s = beta + 0.5 * (c1 + c2);
+  if (s <= 0.0) return 0.0;
+  if (s >= c1 + c2) return 1.0;
+  if (s < c1) return s * s / (2.0 * c1 * c2);
+  if (s <= c2) return (s - 0.5 * c1) / c2;
+  const double t = c1 + c2 - s;
+  return 1.0 - t * t / (2.0 * c1 * c2);
+}
+
+// Inverse of cut_fraction in beta for 0 < f < 1.
+__device__ inline double cut_offset(double nx, double ny, double hx, double hy, double f) {
+  double c1 = fabs(nx) * hx, c2 = fabs(ny) * hy;
+  if (c1 > c2) { const double t = c1; c1 = c2; c2 = t; }
+  const double f1 = 0.5 * c1 / c2;  // fraction at s = c1
+  double s;
+  if (f <= f1) s = sqrt(2.0 * c1 * c2 * f);
+  else if (f <= 1.0 - f1) s = f * c2 + 0.5 * c1;
+  else s = c1 + c2 - sqrt(2.0 * c1 * c2 * (1.0 - f));
+  return s - 0.5 * (c1 + c2);
+}
+
+// Candidates: the interface as a graph over x (slopes from the backward,
+// central and forward differences of the column sums of r) and over y (row
+// sums); the body lies on the side given by the sign of the opposite sums
+// (rows bottom vs top, columns left vs right), a family with sign zero is
+// left out. Each candidate line cuts the centre cell at its fraction; the
+// one whose nine cell fractions differ least from r in the sum of squares is
+// taken (the first on ties). Returns false where the centre fraction is not
+// strictly between 0 and 1 or no family exists.
+template <class S, typename T>
+__device__ inline bool elvira_normal(const Params& P, const T* __restrict__ U, int i, int j, int k, double n[3]) {
+  double f[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) f[a][b] = r_block<S>(P, U, i + a - 1, j + b - 1, k);
+  const double fc = f[1][1];
+  if (!(fc > 0.0 && fc < 1.0)) return false;
+  const double hx = P.dx[0], hy = P.dx[1];
+  double H[3], Wr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) H[a] = hy * (f[a][0] + f[a][1] + f[a][2]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) Wr[b] = hx * (f[0][b] + f[1][b] + f[2][b]);
+  const double sy = Wr[2] > Wr[0] ? 1.0 : (Wr[2] < Wr[0] ? -1.0 : 0.0);
+  const double sx = H[2] > H[0] ? 1.0 : (H[2] < H[0] ? -1.0 : 0.0);
+  double best = 0.0;
+  bool found = false;
+  for (int c = 0; c < 6; ++c) {
+    const bool colf = c < 3;
+    const double sg = colf ? sy : sx;
+    if (sg == 0.0) continue;
+    const double* A = colf ? H : Wr;
+    const double h = colf ? hx : hy;
+    const int m = c % 3;
+    const double sl = m == 0 ? (A[1] - A[0]) / h : (m == 1 ? (A[2] - A[0]) / (2.0 * h) : (A[2] - A[1]) / h);
+    const double vx = colf ? -sl : -sg, vy = colf ? -sg : -sl;
+    const double mag = sqrt(vx * vx + vy * vy);
+    const double nx = vx / mag, ny = vy / mag;
+    const double beta = cut_offset(nx, ny, hx, hy, fc);
+    double err = 0.0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+      for (int b = -1; b <= 1; ++b) {
+        const double e = cut_fraction(nx, ny, hx, hy, beta - nx * a * hx - ny * b * hy) - f[a + 1][b + 1];
+        err += e * e;
+      }
+    if (!found || err < best) {
+      best = err;
+      found = true;
+      n[0] = nx;
+      n[1] = ny;
+      n[2] = 0.0;
+    }
+  }
+  return found;
+}
+
+// Normal of a rigid cell for seeding: ELVIRA in 2D when selected and
+// defined, otherwise Youngs.
+template <class S, typename T>
+__device__ inline bool band_normal(const Params& P, const T* __restrict__ U, int i, int j, int k, double n[3]) {
+  if constexpr (S::D == 2) {
+    if (P.normal == NORMAL_ELVIRA && elvira_normal<S>(P, U, i, j, k, n)) return true;
+  }
+  return youngs_normal<S>(P, U, i, j, k, n);
+}
+
+// Seeding geometry of one rigid cell (Sec. 3.2 steps 1-2): outward normal,
 // probe along n at 1, 1.5, ..., 4 dx (or the fixed 1.5 dx); the first point
 // whose enclosing cells with a nonzero interpolation weight are all interior
 // with r <= 0.5 is used. It depends on r only, so for a static body it is
@@ -600,7 +712,7 @@ __global__ __launch_bounds__(256) void k_band(Params P, const T* __restrict__ U,
   int pi[3];
   decode(P, c, pi[0], pi[1], pi[2]);
   double n[3];
-  if (!youngs_normal<S>(P, U, pi[0], pi[1], pi[2], n)) return;
+  if (!band_normal<S>(P, U, pi[0], pi[1], pi[2], n)) return;
   const int nprobe = P.probe == PROBE_FIXED ? 1 : 7;
   int best = -1;
   int blo[3] = {0, 0, 0};

@@ -21,6 +21,7 @@ enum { REC_MUSCL = 0, REC_BVD_THINC = 1 };
 enum { RS_HLLC = 0, RS_HLLC_LM = 1 };
 enum { SEED_ORIGINAL = 0, SEED_RIEMANN = 1, SEED_NONE = 2 };
 enum { PROBE_STEPOUT = 0, PROBE_FIXED = 1 };
+enum { NORMAL_YOUNGS = 0, NORMAL_ELVIRA = 1 };
 
 // Reciprocal from the hardware estimate refined by two Newton steps (FP64;
 // within an ulp or two of 1/x), or the single-precision hardware
@@ -55,6 +56,7 @@ struct Params {
   double dx[3], inv_dx[3], x0[3], dmin;
   int bc[6];
   int recon, riemann, seed, probe, plastic;
+  int normal;
   double cosh_b, inv_sinh_b, tanh_b, beta;
   double lm_mach;
   double exc[14];         // 1/k!, k = 0..13 (exponential series, kept in scalar registers)

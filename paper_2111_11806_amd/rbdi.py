@@ -20,6 +20,7 @@ RECON = {"muscl": 0, "bvd_thinc": 1}
 RIEMANN = {"hllc": 0, "hllc_lm": 1}
 SEED = {"original": 0, "riemann": 1, "none": 2}
 PROBE = {"stepout": 0, "fixed": 1}
+NORMAL = {"youngs": 0, "elvira": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 
 RBDI_OK = 0
@@ -37,7 +38,8 @@ class Desc(ctypes.Structure):
                 ("origin", ctypes.c_double * 3), ("nmat", ctypes.c_int), ("solid", ctypes.c_int),
                 ("bc", ctypes.c_int * 6), ("recon", ctypes.c_int), ("riemann", ctypes.c_int),
                 ("seed", ctypes.c_int), ("probe", ctypes.c_int), ("plastic", ctypes.c_int),
-                ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("thinc_beta", ctypes.c_double), ("lm_mach", ctypes.c_double), ("precision", ctypes.c_int),
+                ("normal", ctypes.c_int)]
 
 
 class Eos(ctypes.Structure):
@@ -184,6 +186,7 @@ def make_desc(prob, precision="fp64") -> Desc:
     d.thinc_beta = prob.thinc_beta
     d.lm_mach = prob.lm_mach
     d.precision = PRECISION[precision]
+    d.normal = NORMAL[prob.normal]
     return d
 
 

@@ -43,3 +43,24 @@ def test_bad_arguments_fail_without_gpu_work():
     assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"dim" in lib.rbdi_last_error()
     assert lib.rbdi_create(None, ctypes.byref(h)) == -1
+
+
+def test_elvira_outside_2d_is_rejected():
+    """ELVIRA normals exist in 2D only; other dimensions fail at create,
+    before any device work."""
+    from paper_2111_11806_amd import rbdi
+    lib = rbdi.load()
+    h = ctypes.c_void_p()
+    d = rbdi.Desc()
+    d.dim = 3
+    for a in range(3):
+        d.n[a] = 8
+        d.dx[a] = 0.125
+    d.nmat = 1
+    d.thinc_beta = 1.6
+    d.lm_mach = 0.1
+    d.normal = 1
+    assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"ELVIRA" in lib.rbdi_last_error()
+    d.normal = 2
+    assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1

@@ -5,6 +5,8 @@ them), against the CPU FP64 oracle:
 - Mach 2.8 shock over a rigid cylinder, 1024 x 512 (FP64 <= 1e-10, FP32
   <= 1e-4 relative L1 per conserved field);
 - air/water with a moving rigid ellipse, 2048 x 1024 (FP64 <= 1e-10);
+- Mach 1.7 shock onto a 25-degree wedge with ELVIRA normals, 1200 x 800
+  (FP64 <= 1e-10);
 - 3D copper indenter, 256^3, one step (FP64 <= 1e-10; FP32 with the
   surrogate closure <= 1e-4 per quantity, vectors and tensors whole).
 
@@ -70,6 +72,22 @@ def test_air_water_full_size_fp64(rbdi):
     s = rbdi.Solver(prob, "fp64")
     s.run(dts)
     assert s.status()["nonphysical"] == 0
+    rl = rel_l1(s.get_state_cons(), orc.get_state_cons())
+    announce("  rel L1 " + np.array2string(rl, precision=2))
+    assert np.all(rl <= 1e-10), rl
+
+
+def test_wedge_full_size_elvira_fp64_device_dt(rbdi):
+    """Mach 1.7 shock and 25-degree wedge on 1200 x 800 (the uniform grid of
+    the finest of three levels), ELVIRA normals, 100 device-CFL steps."""
+    prob = inputs.wedge(1200, 800)
+    announce("wedge 1200x800 fp64 elvira, 100 device-CFL steps")
+    orc = oracle.Oracle(prob)
+    orc.run(nsteps=100)
+    s = rbdi.Solver(prob, "fp64")
+    s.advance(prob.cfl, 100, prob.t_end)
+    st = s.status()
+    assert st["steps"] == 100 and abs(st["t"] - orc.t) <= 1e-12 * orc.t
     rl = rel_l1(s.get_state_cons(), orc.get_state_cons())
     announce("  rel L1 " + np.array2string(rl, precision=2))
     assert np.all(rl <= 1e-10), rl
