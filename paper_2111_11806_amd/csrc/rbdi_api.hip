@@ -207,7 +207,7 @@ struct Impl {
     const unsigned nseg = (unsigned)((P.n[DIR] + kOut - 1) / kOut);
     const unsigned gx = (unsigned)((P.n[0] + TC - 1) / TC);
     const dim3 grid = DIR == 1 ? dim3(gx, nseg, (unsigned)P.n[2]) : dim3(gx, (unsigned)P.n[1], nseg);
-    launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE>, grid, dim3(256), 0, P, Uin, static_cast<T*>(h->D), h->sc,
+    launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE>, grid, dim3(kTileThreads), 0, P, Uin, static_cast<T*>(h->D), h->sc,
            (const double*)h->cflpart, A);
   }
   static void sources_mlp(rbdi_handle* h, T* Uout, const StepArgs& A, int stage) {
@@ -896,7 +896,7 @@ struct BImpl {
   template <int DIR, int MODE, bool REDUCE>
   static void tile_l(rbdi_batch* b, const BatchArgs& B, int grid, int tc, const BatchItem* items) {
     const size_t lds = (size_t)S::NF * tc * kRS * sizeof(T);
-    hipLaunchKernelGGL((kb_sweep_tile<S, T, DIR, MODE, REDUCE>), dim3(grid), dim3(256), lds, b->stream,
+    hipLaunchKernelGGL((kb_sweep_tile<S, T, DIR, MODE, REDUCE>), dim3(grid), dim3(kTileThreads), lds, b->stream,
                        (const BatchInst<T>*)b->inst, items, B, tc);
   }
   static void tile(rbdi_batch* b, int dir, int which, const BatchArgs& B, int grid, int tc) {

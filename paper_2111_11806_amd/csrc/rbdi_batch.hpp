@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void kb_sweep_x(const BatchInst<T>* __restrict
 
 // Tile of tc columns in dynamic LDS (S::NF * tc * kRS values).
 template <class S, typename T, int DIR, int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) void kb_sweep_tile(const BatchInst<T>* __restrict__ I,
+__global__ __launch_bounds__(kTileThreads) void kb_sweep_tile(const BatchInst<T>* __restrict__ I,
                                                     const BatchItem* __restrict__ items, BatchArgs B, int tc) {
   extern __shared__ double lds_dyn[];
   T* tile = reinterpret_cast<T*>(lds_dyn);

@@ -24,6 +24,7 @@ constexpr int kOut = 58;       // cells updated per wavefront
 constexpr int kHalo = 3;
 constexpr int kWPB = 4;        // wavefronts per block in 2D/3D x sweeps (default)
 constexpr int kMaxWPB = 4;     // largest x-sweep block (partial capacity)
+constexpr int kTileThreads = 256;  // block size of the y/z tile sweeps
 
 // Device-resident scalars of one instance. Per-step values live in two
 // slots indexed by the parity of the step: during step n (parity p) slot p
@@ -456,25 +457,44 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
   else { j = by; seg = bz; k = 0; }
   const int nd = P.n[DIR];
   const int base = seg * kOut - kHalo;
-  for (int e = threadIdx.x; e < TC * kWave; e += blockDim.x) {
-    const int c = e % TC, r = e / TC;
-    const int x = x0 + c;
-    if (x >= P.n[0]) continue;
-    const int pos = base + r;
-    const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
-    int src, face;
-    if (ghost_map(P, DIR, posl, src, face) == 2) continue;
-    int p3[3] = {x, j, k};
-    p3[DIR] = src;
-    const long long cell = cell_index(P, p3[0], p3[1], p3[2]);
+  // Tile load: each thread owns TC * kWave / kTileThreads cells; the loads of
+  // a group of them are all issued before the first LDS write, so their
+  // latencies overlap (a group holds at most about 24 values).
+  constexpr int kG = 24 / S::NF > 0 ? 24 / S::NF : 1;
+  const int nper = TC * kWave / kTileThreads;
+  for (int it0 = 0; it0 < nper; it0 += kG) {
+    T v[kG][S::NF];
+    int dst[kG];
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + r] = Uin[q * P.fs + cell];
+    for (int g = 0; g < kG; ++g) {
+      dst[g] = -1;
+      const int e = threadIdx.x + (it0 + g) * kTileThreads;
+      const int c = e % TC, r = e / TC;
+      const int x = x0 + c;
+      const int pos = base + r;
+      const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
+      int src = 0, face;
+      if (it0 + g < nper && x < P.n[0] && ghost_map(P, DIR, posl, src, face) != 2) {
+        int p3[3] = {x, j, k};
+        p3[DIR] = src;
+        const long long cell = cell_index(P, p3[0], p3[1], p3[2]);
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q) v[g][q] = Uin[q * P.fs + cell];
+        dst[g] = c * kRS + r;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kG; ++g)
+      if (dst[g] >= 0) {
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q) tile[q * TC * kRS + dst[g]] = v[g][q];
+      }
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const double tc = sc->t[A.par] - sc->t_motion;
-  for (int c = wave; c < TC; c += blockDim.x / kWave) {
+  for (int c = wave; c < TC; c += kTileThreads / kWave) {
     const int x = x0 + c;
     if (x >= P.n[0]) break;  // uniform in the wavefront
     const int pos = base + lane;
@@ -503,7 +523,7 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TC * kWave; e += blockDim.x) {
+  for (int e = threadIdx.x; e < TC * kWave; e += kTileThreads) {
     const int c = e % TC, r = e / TC;
     const int x = x0 + c;
     const int pos = base + r;
@@ -521,7 +541,7 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
 }
 
 template <class S, typename T, int DIR, int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tile_sweep_waves<S>()))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(tile_sweep_waves<S>()))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                    DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                    StepArgs A) {
   constexpr int TC = tile_cols<S, T>();
