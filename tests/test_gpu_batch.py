@@ -68,6 +68,24 @@ def test_batch_equals_single_bitwise(rbdi):
         assert s.status()["t"] == st[k]["t"]
 
 
+def test_batch_elvira_members_vs_oracle(rbdi):
+    """Members with ELVIRA normals (bands built per member at batch creation):
+    batched == single-instance bitwise, and each member matches the oracle."""
+    probs = _small(count=4, seed=23)
+    for p in probs:
+        p.normal = "elvira"
+    announce("batch elvira, %d instances, sizes %s" % (len(probs), [p.n[:2] for p in probs]))
+    bat, st, _ = _run_batch(rbdi, probs, "fp64", 15)
+    for k, p in enumerate(probs):
+        s = rbdi.Solver(p, "fp64")
+        s.advance(p.cfl, 15)
+        assert np.array_equal(s.get_state_cons(), bat[k]), p.name
+        orc = oracle.Oracle(p)
+        orc.run(nsteps=15)
+        assert abs(orc.t - st[k]["t"]) <= 1e-12 * orc.t
+        assert np.all(rel_l1(bat[k], orc.get_state_cons()) <= TOL64)
+
+
 def test_batch_fixed_dt_equals_single_bitwise(rbdi):
     probs = _small(count=4, seed=11)
     dts = [[0.8 * rbdi.Solver(p, "fp32").compute_dt(p.cfl)] * 6 for p in probs]

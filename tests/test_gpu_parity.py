@@ -174,6 +174,56 @@ def test_sharp_ramp_elvira_seeding(rbdi):
     _check(o1, g1, TOL64)
 
 
+def _uniform_stream_with_body(prob, sdf, bc, stream=(1.2, 0.4)):
+    W = np.zeros_like(prob.W0)
+    W[0] = 1.0
+    W[1] = stream[0]
+    W[2] = stream[1]
+    W[3] = 1.0
+    prob.W0 = W
+    prob.sdf = sdf
+    prob.bc = bc
+    return prob
+
+
+def test_elvira_body_across_periodic_boundaries(rbdi):
+    """A rotated ellipse cut by both periodic boundaries in a uniform stream:
+    ELVIRA's 3x3 blocks wrap around the domain edges and corners."""
+    prob = inputs.wedge(96, 64, normal="elvira")
+    nx, ny = prob.n[0], prob.n[1]
+    dx, dy = prob.dx[0], prob.dx[1]
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(x, y)
+    Lx, Ly = nx * dx, ny * dy
+    best = None
+    for sx in (-Lx, 0.0, Lx):          # periodic images of the body
+        for sy in (-Ly, 0.0, Ly):
+            d = inputs.ellipse_sdf(X + sx, Y + sy, 0.05, 0.1, 0.3, 0.18, angle=0.6)
+            best = d if best is None else np.minimum(best, d)
+    prob = _uniform_stream_with_body(prob, best[None], ["periodic"] * 4 + ["transmissive"] * 2)
+    prob.bc_states = {}
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=40)
+    _check(orc, gpu, TOL64)
+    assert gpu.status()["seeded"] > 0
+
+
+def test_elvira_body_on_dirichlet_inflow(rbdi):
+    """A cylinder cut by the Dirichlet inflow face (its ghost r is the
+    boundary state's) and by the reflective bottom (corner blocks)."""
+    prob = inputs.wedge(90, 60, normal="elvira")
+    nx, ny = prob.n[0], prob.n[1]
+    x = (np.arange(nx) + 0.5) * prob.dx[0]
+    y = (np.arange(ny) + 0.5) * prob.dx[1]
+    X, Y = np.meshgrid(x, y)
+    sdf = np.sqrt((X - 0.05) ** 2 + (Y - 0.1) ** 2) - 0.35
+    prob = _uniform_stream_with_body(prob, sdf[None], ["dirichlet", "transmissive", "reflective",
+                                                        "transmissive", "transmissive", "transmissive"])
+    prob.bc_states = {0: np.array([1.0, 1.2, 0.4, 1.0, 0.0])}
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=40)
+    _check(orc, gpu, TOL64)
+
+
 def test_cfl_dt_matches(rbdi):
     prob = inputs.shock_cylinder(200, 100)
     orc = oracle.Oracle(prob)
