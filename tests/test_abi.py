@@ -64,3 +64,35 @@ def test_elvira_outside_2d_is_rejected():
     assert b"ELVIRA" in lib.rbdi_last_error()
     d.normal = 2
     assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
+
+
+def _desc2d(rbdi, nx, ny):
+    d = rbdi.Desc()
+    d.dim = 2
+    d.n[0], d.n[1], d.n[2] = nx, ny, 1
+    d.dx[0] = d.dx[1] = d.dx[2] = 0.01
+    d.nmat = 1
+    d.thinc_beta = 1.6
+    d.lm_mach = 0.1
+    return d
+
+
+def test_empty_and_oversized_grids_are_rejected():
+    """Degenerate sizes fail at create, before any device work: an empty grid,
+    2^31 cells (band indices are 32-bit), a reflective face on fewer cells
+    than the 3-cell halo."""
+    from paper_2111_11806_amd import rbdi
+    lib = rbdi.load()
+    h = ctypes.c_void_p()
+    for nx, ny in ((0, 8), (8, 0), (-1, 8)):
+        assert lib.rbdi_create(ctypes.byref(_desc2d(rbdi, nx, ny)), ctypes.byref(h)) == -1
+        assert b"grid size" in lib.rbdi_last_error()
+    assert lib.rbdi_create(ctypes.byref(_desc2d(rbdi, 1 << 16, 1 << 15)), ctypes.byref(h)) == -1
+    assert b"too many cells" in lib.rbdi_last_error()
+    d = _desc2d(rbdi, 8, 2)
+    d.bc[2] = d.bc[3] = 1  # reflective y faces on 2 rows
+    assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"reflective" in lib.rbdi_last_error()
+    d = _desc2d(rbdi, 8, 8)
+    d.n[2] = 2  # unused dimension must be 1
+    assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1

@@ -86,6 +86,44 @@ def test_ragged_1d_sizes(rbdi, n):
     _check(orc, gpu, TOL64)
 
 
+@pytest.mark.parametrize("nx,ny", [(3, 3), (58, 58), (59, 117), (117, 59), (130, 5)])
+def test_ragged_2d_sizes(rbdi, nx, ny):
+    """2D grids below, at and around the 58-cell x segment and the 58-row y
+    segment (tiles of 16 columns with ragged last tiles), with the cylinder,
+    Dirichlet inflow and reflective walls, 20 steps."""
+    prob = inputs.shock_cylinder(nx, ny)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=20)
+    _check(orc, gpu, TOL64)
+
+
+@pytest.mark.parametrize("n", [(59, 5, 17), (3, 61, 4), (17, 9, 60)])
+def test_ragged_3d_sizes(rbdi, n):
+    """Non-cubic 3D grids with ragged tiles along every direction: a
+    pressure pulse over a static sphere, reflective and transmissive faces."""
+    nx, ny, nz = n
+    dx = 1.0 / max(n)
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    z = (np.arange(nz) + 0.5) * dx
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    W = np.zeros((6, nz, ny, nx))
+    hot = X + 0.5 * Y + 0.25 * Z < 0.3
+    W[0] = np.where(hot, 2.0, 1.0)
+    W[1] = np.where(hot, 0.6, 0.0)
+    W[2] = np.where(hot, -0.2, 0.0)
+    W[3] = np.where(hot, 0.1, 0.0)
+    W[4] = np.where(hot, 2.5, 1.0)
+    c = (0.5 * nx * dx, 0.5 * ny * dx, 0.5 * nz * dx)
+    sdf = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - 0.3 * min(n) * dx
+    prob = inputs.Problem(name="ragged3d", dim=3, n=(nx, ny, nz), dx=(dx, dx, dx), origin=(0.0, 0.0, 0.0),
+                          materials=[inputs.ideal(1.4)], solid=False,
+                          bc=["transmissive", "transmissive", "reflective", "transmissive", "reflective",
+                              "reflective"],
+                          W0=W, sdf=sdf, width=1.0, recon="bvd_thinc", riemann="hllc", cfl=0.4, t_end=1.0)
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=12)
+    _check(orc, gpu, TOL64)
+
+
 def test_two_phase_1d_water_air(rbdi):
     eps = 1e-6
     mats = [inputs.stiffened(1.4, 0.0), inputs.stiffened(4.4, 6e8)]
