@@ -203,10 +203,6 @@ struct Impl {
     const unsigned w = (unsigned)x_wpb(P);
     return dim3((nseg + w - 1) / w, (unsigned)P.n[1], (unsigned)P.n[2]);
   }
-  static int x_partials(const Params& P) {
-    const dim3 g = x_grid(P);
-    return (int)(g.x * g.y * g.z) * x_wpb(P);
-  }
   static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
     launch(h, 0, k_sweep_x<S, T>, x_grid(h->P), dim3(kWave * x_wpb(h->P)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
            h->sc, h->cflpart, A, b, stage);
