@@ -206,6 +206,32 @@ def run_copper(n, steps, warmup):
     return out
 
 
+def run_wedge(steps, warmup, normal="elvira"):
+    """Mach 1.7 shock onto the 25-degree wedge, 1200 x 800 (the uniform grid
+    of the finest of three levels), ELVIRA normals, FP64, device CFL steps."""
+    import torch
+    from paper_2111_11806_amd import inputs, rbdi
+    prob = inputs.wedge(1200, 800, normal=normal)
+    stream = torch.cuda.current_stream()
+    s = rbdi.Solver(prob, "fp64", stream=stream)
+    s.advance(prob.cfl, warmup, prob.t_end)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.advance(prob.cfl, steps, prob.t_end)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = s.status(raise_on_error=False)
+    out = {"workload": "wedge (Mach 1.7, 25 deg)", "nx": 1200, "ny": 800, "cells": prob.ncells, "normal": normal,
+           "dtype": "f64", "steps": steps, "ms_per_step": round(ms, 4), "value": prob.ncells / (ms * 1e-3),
+           "unit": "cell-updates/s", "t_reached": st["t"], "band_cells": st["band_cells"],
+           "nonphysical": st["nonphysical"]}
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +247,8 @@ def main():
     ap.add_argument("--copper-n", type=int, default=256)
     ap.add_argument("--copper-steps", type=int, default=5)
     ap.add_argument("--no-copper", action="store_true")
+    ap.add_argument("--wedge-steps", type=int, default=500)
+    ap.add_argument("--no-wedge", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -300,6 +328,9 @@ def main():
 
     if not args.no_copper:
         out["copper"] = run_copper(args.copper_n, args.copper_steps, 2)
+
+    if not args.no_wedge:
+        out["wedge"] = run_wedge(args.wedge_steps, 20)
 
     if not args.no_cpu_baseline:
         import oracle
