@@ -402,11 +402,11 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
 // Occupancy requests (waves per SIMD) of the single-gas sweep kernels: the
 // sweeps are latency-bound chains of FP64 operations, so more resident
 // wavefronts hide more of each chain, as long as the register budget does
-// not force spills (measured: five for the 2D x sweep; the LDS tile holds
-// the y/z sweeps at three). Other systems: the compiler's choice (1 = no
-// request).
+// not force spills (measured on the 2D x sweep: four, 128 registers without
+// spills, beats five with spills and six; the LDS tile holds the y/z sweeps
+// at three). Other systems: the compiler's choice (1 = no request).
 template <class S>
-constexpr int x_sweep_waves() { return (S::S || S::N != 1) ? 1 : (S::D == 2 ? 5 : 4); }
+constexpr int x_sweep_waves() { return (S::S || S::N != 1) ? 1 : 4; }
 template <class S>
 constexpr int tile_sweep_waves() { return (S::S || S::N != 1) ? 1 : 3; }
 
