@@ -96,3 +96,23 @@ def test_empty_and_oversized_grids_are_rejected():
     d = _desc2d(rbdi, 8, 8)
     d.n[2] = 2  # unused dimension must be 1
     assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
+
+
+def test_bench_traffic_needs_matching_sources(tmp_path, monkeypatch):
+    """The benchmark reports measured HBM traffic only from a counter summary
+    taken on the current kernel sources and grid."""
+    import bench
+    good = bench.measured_traffic(524288)
+    if good is not None:
+        assert bench.measured_traffic(524288 * 2) is None
+    fake = tmp_path / "traffic.txt"
+    good_keys = ["source_sha1: 0000", "cells: 524288", "copy_bytes_read: 1", "copy_bytes_written: 1",
+                 "copy_fetch_kib: 1", "copy_write_kib: 1", "sweep_y_fetch_kib: 1", "sweep_y_write_kib: 1",
+                 "sweep_x_fetch_kib: 1", "sweep_x_write_kib: 1"]
+    fake.write_text("\n".join(good_keys) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake))
+    assert bench.measured_traffic(524288) is None          # other sources
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000")
+    # 2 + 2 KiB counted, each KiB worth 1 byte by the copy scale: 4 bytes
+    assert bench.measured_traffic(524288) == 4.0
+    assert bench.measured_traffic(1000) is None            # other grid

@@ -306,6 +306,40 @@ def test_air_water_moving_ellipse(rbdi):
     _check(orc, gpu, TOL64)
 
 
+def test_air_water_moving_ellipse_elvira(rbdi):
+    """The moving ellipse with ELVIRA normals: the band (normals, probes) is
+    rebuilt every step from the advected r."""
+    prob = inputs.air_water(192, 96)
+    prob.normal = "elvira"
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=40)
+    _check(orc, gpu, TOL64)
+
+
+def test_diagnostics_leave_the_state_alone(rbdi):
+    """Kernel replays, timing and operator evaluation write only scratch
+    buffers: the state and the following steps are bitwise those of a
+    solver that never ran them."""
+    prob = inputs.shock_cylinder(160, 80)
+    a = rbdi.Solver(prob, "fp64")
+    b = rbdi.Solver(prob, "fp64")
+    a.advance(prob.cfl, 10)
+    b.advance(prob.cfl, 10)
+    a.set_kernel_timing(True)
+    a.advance(prob.cfl, 3)
+    a.kernel_times()
+    a.set_kernel_timing(False)
+    b.advance(prob.cfl, 3)
+    u0 = a.get_state_cons()
+    a.kernel_replay(0, 5)
+    a.kernel_replay(1, 5)
+    a.eval_rhs()
+    assert np.array_equal(a.get_state_cons(), u0)
+    a.advance(prob.cfl, 5)
+    b.advance(prob.cfl, 5)
+    assert np.array_equal(a.get_state_cons(), b.get_state_cons())
+    assert a.status()["t"] == b.status()["t"]
+
+
 def test_air_water_fp32(rbdi):
     """FP32 path on the two stiffened gases (p_inf of water 6e8 Pa against
     p = 1e5 Pa): the stored energy E~ = rho E - B(phi) keeps the pressure
