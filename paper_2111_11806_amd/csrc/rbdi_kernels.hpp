@@ -246,9 +246,16 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
     const T rmL = shdn<Z>(c.mL), rtL = shdn<Z>(c.tL);
     bvd(P, lmR, ltR, c, rmL, rtL, sL[q], sR[q]);
   }
-  if (!admissible<S>(P, sL) || !admissible<S>(P, sR)) {
+  // first-order fallback; skipped by the whole wavefront when no lane needs
+  // it (the common case) instead of selects on every lane (1.3% off a 2D
+  // FP64 step)
+  const bool bad = !admissible<S>(P, sL) || !admissible<S>(P, sR);
+  if (__any(bad)) {
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) { sL[q] = W[q]; sR[q] = W[q]; }
+    for (int q = 0; q < S::NF; ++q) {
+      sL[q] = bad ? W[q] : sL[q];
+      sR[q] = bad ? W[q] : sR[q];
+    }
   }
   // face pos+1/2: left state = this cell's right face, right state = the
   // next cell's left face
