@@ -233,6 +233,24 @@ RBDI_API int rbdi_kernel_times(rbdi_handle* h, double* ms, long long* launches);
  * the handle's first step or while it belongs to a batch. Synchronises. */
 RBDI_API int rbdi_kernel_replay(rbdi_handle* h, int cls, int reps, double* us);
 
+/* Wavefronts per block of the x sweep of a 2D or 3D instance: 1, 2 or 4; 0
+ * restores the library's choice (2D: 4 or 2, whichever leaves fewer idle
+ * wavefronts at the end of a row; 3D: 4). Results do not depend on it.
+ * BAD_ARG for other values (and for more than 1 in 1D), NOT_READY for a
+ * batch member. */
+RBDI_API int rbdi_set_x_waves(rbdi_handle* h, int waves);
+
+/* Autotuner of one instance: from the current state, time nsteps steps with
+ * the device CFL time step (CFL number cfl) for each x-sweep block size (1,
+ * 2 and 4 wavefronts; 1D: one), putting back after each trial everything a
+ * step changes (state, time, step counters, CFL partials), and keep the
+ * fastest as with rbdi_set_x_waves. best: the chosen size; us: its mean time
+ * per step in microseconds. The state after the call is the one before it.
+ * Allocates one state-sized device buffer for the duration of the call;
+ * synchronises. BAD_ARG for nsteps < 1, cfl <= 0 or null outputs; NOT_READY
+ * without a state or for a batch member. */
+RBDI_API int rbdi_autotune(rbdi_handle* h, double cfl, int nsteps, int* best, double* us);
+
 /* Unit-level evaluation of single device functions on n states (host
  * arrays, FP64, state-major: n x nfields), for parity checks of the
  * building blocks of the step. what = 0: HLLC flux along dir of the face

@@ -64,6 +64,7 @@ struct rbdi_handle {
   rbdi_batch* owner = nullptr;  // batch that steps this instance, if any
   rbdi_mlp* mlp = nullptr;      // surrogate closure of the elastoplastic sources, if set
   long long enqueued = 0;       // steps enqueued by this handle
+  int x_waves = 0;              // x-sweep wavefronts per block (0: the library's rule)
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;   // start/stop pairs
@@ -191,20 +192,22 @@ struct Impl {
   // fewer idle wavefronts at the end of a row (4 on ties; measured on the
   // 1024-cell rows of the shock/cylinder grid: 18 segments run 1.4% faster
   // per step as 9 blocks of 2 than as 5 blocks of 4); 4 in 3D.
-  static int x_wpb(const Params& P) {
+  static int x_wpb(const rbdi_handle* h) {
     if (S::D == 1) return 1;
+    if (h->x_waves > 0) return h->x_waves;  // rbdi_set_x_waves / rbdi_autotune
     if (S::D == 3) return kWPB;
-    const int nseg = (P.n[0] + kOut - 1) / kOut;
+    const int nseg = (h->P.n[0] + kOut - 1) / kOut;
     const int idle4 = (nseg + 3) / 4 * 4 - nseg, idle2 = (nseg + 1) / 2 * 2 - nseg;
     return idle2 < idle4 ? 2 : 4;
   }
-  static dim3 x_grid(const Params& P) {
+  static dim3 x_grid(const rbdi_handle* h) {
+    const Params& P = h->P;
     const unsigned nseg = (unsigned)((P.n[0] + kOut - 1) / kOut);
-    const unsigned w = (unsigned)x_wpb(P);
+    const unsigned w = (unsigned)x_wpb(h);
     return dim3((nseg + w - 1) / w, (unsigned)P.n[1], (unsigned)P.n[2]);
   }
   static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
-    launch(h, 0, k_sweep_x<S, T>, x_grid(h->P), dim3(kWave * x_wpb(h->P)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
+    launch(h, 0, k_sweep_x<S, T>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
            h->sc, h->cflpart, A, b, stage);
   }
   template <int DIR, int MODE, bool REDUCE>
@@ -791,6 +794,86 @@ RBDI_API int rbdi_kernel_replay(rbdi_handle* h, int cls, int reps, double* us) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *us = 1e3 * ms / reps;
+  return check_launch();
+}
+
+RBDI_API int rbdi_set_x_waves(rbdi_handle* h, int waves) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null handle");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4) return fail(RBDI_ERR_BAD_ARG, "x waves must be 0, 1, 2 or 4");
+  if (h->desc.dim == 1 && waves > 1) return fail(RBDI_ERR_BAD_ARG, "1D x sweeps run one wavefront per block");
+  h->x_waves = waves;
+  return RBDI_OK;
+}
+
+RBDI_API int rbdi_autotune(rbdi_handle* h, double cfl, int nsteps, int* best, double* us) {
+  if (!h || !best || !us || nsteps < 1 || !(cfl > 0.0)) return fail(RBDI_ERR_BAD_ARG, "bad autotune argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
+  if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
+  // everything a step changes that a later step reads: the state (U^n and
+  // the buffer order, which the surrogate pass swaps), the device scalars,
+  // the CFL partials, and the host-side step bookkeeping
+  const size_t state_bytes = (size_t)h->P.fs * h->nf * h->elem;
+  const size_t part_bytes = sizeof(double) * (size_t)h->part_cap;
+  char* save = nullptr;
+  HIP_OK(hipMalloc((void**)&save, state_bytes + part_bytes + sizeof(DevScalars)));
+  void* const u_order[3] = {h->U[0], h->U[1], h->U[2]};
+  const int par = h->par, x0 = h->x_waves;
+  const bool cfl_valid = h->cfl_valid, band_valid = h->band_valid, timing = h->timing;
+  const long long enq = h->enqueued;
+  int rc = RBDI_OK;
+  auto copy = [&](bool out) -> int {
+    char* p = save;
+    void* dst[3] = {p, p + state_bytes, p + state_bytes + part_bytes};
+    void* src[3] = {h->U[0], h->cflpart, h->sc};
+    const size_t sz[3] = {state_bytes, part_bytes, sizeof(DevScalars)};
+    for (int k = 0; k < 3; ++k)
+      if (hipMemcpyAsync(out ? dst[k] : src[k], out ? src[k] : dst[k], sz[k], hipMemcpyDeviceToDevice, h->stream) !=
+          hipSuccess)
+        return fail(RBDI_ERR_HIP, "autotune state copy");
+    return RBDI_OK;
+  };
+  rc = copy(true);
+  const int cands[3] = {1, 2, 4};
+  const int ncand = h->desc.dim == 1 ? 1 : 3;
+  double best_us = 0.0;
+  int best_w = 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(RBDI_ERR_HIP, "autotune events");
+  h->timing = false;
+  for (int c = 0; c < ncand && !rc; ++c) {
+    h->x_waves = h->desc.dim == 1 ? 0 : cands[c];
+    if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(RBDI_ERR_HIP, "autotune event"); break; }
+    for (int s = 0; s < nsteps; ++s) enqueue_step(h, 0.0, cfl, 0.0);
+    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(RBDI_ERR_HIP, "autotune timing");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double t = 1e3 * ms / nsteps;
+    if (c == 0 || t < best_us) { best_us = t; best_w = h->desc.dim == 1 ? 1 : cands[c]; }
+    // back to the state before the call
+    for (int k = 0; k < 3; ++k) h->U[k] = u_order[k];
+    h->par = par;
+    h->cfl_valid = cfl_valid;
+    h->band_valid = band_valid;
+    h->enqueued = enq;
+    if (!rc) rc = copy(false);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->timing = timing;
+  if (hipStreamSynchronize(h->stream) != hipSuccess && !rc) rc = fail(RBDI_ERR_HIP, "autotune sync");
+  (void)hipFree(save);
+  if (rc) {
+    h->x_waves = x0;
+    return rc;
+  }
+  h->x_waves = h->desc.dim == 1 ? 0 : best_w;
+  *best = best_w;
+  *us = best_us;
   return check_launch();
 }
 

@@ -69,6 +69,7 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
            "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
+           "rbdi_set_x_waves", "rbdi_autotune",
            "rbdi_kernel_replay",
            "rbdi_batch_create", "rbdi_batch_destroy", "rbdi_batch_set_stream", "rbdi_batch_set_tuning",
            "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance",
@@ -115,6 +116,8 @@ def load():
     L.rbdi_unit_eval.argtypes = [vp, ip, ip, dp, dp, dp, ip]
     L.rbdi_eval_rhs.argtypes = [vp, ip, dp]
     L.rbdi_kernel_replay.argtypes = [vp, ip, ip, dp]
+    L.rbdi_set_x_waves.argtypes = [vp, ip]
+    L.rbdi_autotune.argtypes = [vp, ctypes.c_double, ip, ctypes.POINTER(ctypes.c_int), dp]
     L.rbdi_batch_create.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.rbdi_batch_destroy.argtypes = [vp]
     L.rbdi_batch_set_stream.argtypes = [vp, vp]
@@ -311,6 +314,19 @@ class Solver:
         out = ctypes.c_double()
         _check(load().rbdi_kernel_replay(self._h, int(cls), int(reps), ctypes.byref(out)))
         return out.value
+
+    def set_x_waves(self, waves):
+        """Wavefronts per x-sweep block (1, 2, 4; 0 = the library's choice)."""
+        _check(load().rbdi_set_x_waves(self._h, int(waves)))
+
+    def autotune(self, cfl, nsteps=10):
+        """Time nsteps steps per x-sweep block size from the current state
+        (restored after each trial) and keep the fastest: (waves, us/step)."""
+        best = ctypes.c_int()
+        us = ctypes.c_double()
+        _check(load().rbdi_autotune(self._h, ctypes.c_double(cfl), int(nsteps), ctypes.byref(best),
+                                    ctypes.byref(us)))
+        return best.value, us.value
 
     def eval_rhs(self, dirmask=7):
         """D(U) of the current state, [nf, nz, ny, nx], over the directions of

@@ -340,6 +340,37 @@ def test_diagnostics_leave_the_state_alone(rbdi):
     assert a.status()["t"] == b.status()["t"]
 
 
+@pytest.mark.parametrize("make,precision", [(lambda: inputs.shock_cylinder(300, 150), "fp64"),
+                                            (lambda: inputs.sod_wall(400), "fp64"),
+                                            (lambda: inputs.air_water(192, 96), "fp32")])
+def test_autotune_keeps_state_and_results(rbdi, make, precision):
+    """rbdi_autotune times real steps per x-sweep block size and puts the
+    state back: afterwards the state, time and step count are those before
+    the call, and further steps are bitwise those of an untuned solver; every
+    block size gives the same results."""
+    prob = make()
+    a = rbdi.Solver(prob, precision)
+    b = rbdi.Solver(prob, precision)
+    a.advance(prob.cfl, 6)
+    b.advance(prob.cfl, 6)
+    u0, st0 = a.get_state_cons(), a.status()
+    best, us = a.autotune(prob.cfl, 4)
+    assert best in ((1,) if prob.dim == 1 else (1, 2, 4)) and us > 0.0
+    st1 = a.status()
+    assert np.array_equal(a.get_state_cons(), u0)
+    assert st1["t"] == st0["t"] and st1["steps"] == st0["steps"] and st1["seeded"] == st0["seeded"]
+    a.advance(prob.cfl, 5)
+    b.advance(prob.cfl, 5)
+    assert np.array_equal(a.get_state_cons(), b.get_state_cons())
+    assert a.status()["t"] == b.status()["t"]
+    if prob.dim > 1:
+        for w in (1, 2, 4):
+            c = rbdi.Solver(prob, precision)
+            c.set_x_waves(w)
+            c.advance(prob.cfl, 11)
+            assert np.array_equal(c.get_state_cons(), b.get_state_cons()), w
+
+
 def test_air_water_fp32(rbdi):
     """FP32 path on the two stiffened gases (p_inf of water 6e8 Pa against
     p = 1e5 Pa): the stored energy E~ = rho E - B(phi) keeps the pressure
