@@ -191,3 +191,27 @@ def test_surrogate_advance_and_gain_timing(rbdi, trained):
     rl = rel_l1(res["surrogate"][1], res["exact"][1])
     assert np.all(rl <= 1e-4), rl
     assert res["surrogate"][2]["steps"] == res["exact"][2]["steps"] == 13
+
+
+def test_autotune_with_the_surrogate_pass(rbdi, trained):
+    """The surrogate pass swaps the state buffers every step; rbdi_autotune
+    puts the buffer order back with the state, so the tuned solver continues
+    bitwise like an untuned one (FP32 copper 24^3 with the network)."""
+    net, _, _ = trained
+    prob = inputs.copper_indenter(24)
+    a = rbdi.Solver(prob, "fp32")
+    b = rbdi.Solver(prob, "fp32")
+    a.set_surrogate(net)
+    b.set_surrogate(net)
+    a.advance(prob.cfl, 3)
+    b.advance(prob.cfl, 3)
+    u0, st0 = a.get_state_cons(), a.status()
+    best, us = a.autotune(prob.cfl, 3)
+    assert best in (1, 2, 4) and us > 0.0
+    st1 = a.status()
+    assert np.array_equal(a.get_state_cons(), u0)
+    assert st1["t"] == st0["t"] and st1["surr_net"] == st0["surr_net"]
+    a.advance(prob.cfl, 4)
+    b.advance(prob.cfl, 4)
+    assert np.array_equal(a.get_state_cons(), b.get_state_cons())
+    assert a.status()["surr_net"] == b.status()["surr_net"]
