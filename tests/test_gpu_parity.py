@@ -182,6 +182,15 @@ def test_wedge_mach17(rbdi, normal):
     assert np.allclose(Fg, Fo, rtol=1e-10, atol=1e-12 * np.abs(Fo).max())
 
 
+def test_wedge_elvira_rectangular_cells(rbdi):
+    """ELVIRA with dx != dy (150 x 80 on 3 x 2: cells 0.02 x 0.025), where
+    the column and row sums carry different cell sizes."""
+    prob = inputs.wedge(150, 80)
+    assert prob.dx[0] != prob.dx[1]
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=100)
+    _check(orc, gpu, TOL64)
+
+
 def test_wedge_mach10_elvira(rbdi):
     """Mach 10 shock onto the 30-degree wedge (double Mach reflection case),
     150 x 100, 80 steps, Riemann seeding."""
