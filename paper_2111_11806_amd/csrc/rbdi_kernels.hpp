@@ -376,8 +376,14 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   if (outlane) {
     const long long c = cell_index(P, pos, j, k);
     if (S::D > 1) {
+      // with a static body r's operator is zero and the y/z sweeps do not
+      // store its row of D: the loaded value is discarded by a select (a
+      // branch around the loads measured slower than the bytes it saves)
 #pragma unroll
-      for (int q = 0; q < S::NF; ++q) d[q] = Dacc[q * P.fs + c] + d[q];
+      for (int q = 0; q < S::NF; ++q) {
+        const T dq = Dacc[q * P.fs + c];
+        d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
+      }
     }
     if (A.rhs_only) {
 #pragma unroll
@@ -559,6 +565,7 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
     const long long cell = cell_index(P, p3[0], p3[1], p3[2]);
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) {
+      if (q == S::R && P.r_static) continue;  // zero; the x sweep ignores this row
       const T v = tile[(q * TC + c) * kRS + r];
       if (MODE == 0) Dacc[q * P.fs + cell] = v;
       else Dacc[q * P.fs + cell] += v;
