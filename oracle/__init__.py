@@ -17,15 +17,25 @@ What pins each part of the oracle (tests marked ``not gpu``):
   stiffened-gas identities, pure-cell limits, water sound speed.
 * THINC candidates (Sec. 3.1): cell average recomputed by quadrature, face
   values bounded, MUSCL slope against the van Leer formula on hand cases.
+* BVD selection (Sec. 3.1): hand-computed total-boundary-variation cases
+  (a smeared step takes THINC, a linear ramp keeps MUSCL, a tie keeps MUSCL,
+  each neighbour face enters with its own scheme), and a contact advected
+  once around a periodic box: sharper and closer to the exact profile than
+  with MUSCL.
 * HLLC (Sec. 3.1): consistency F(U,U) = F(U), contact preservation,
-  equality of the central (LM) form with phi=1 and the Toro form.
+  equality of the central (LM) form with phi=1 and the Toro form; HLLC-LM
+  (Sec. 4.3): the numerical pressure of a symmetric compression face scales
+  as Ma with HLLC and as Ma^2 with HLLC-LM below the Mach limit.
 * Reduced system end to end: exact Riemann solutions (Sod; stiffened-gas
   water/air), the exact Sod-and-wall solution with the reflected shock and its
   interaction with the contact, the Rankine-Hugoniot moving piston,
   quiescent preservation around a static body (bitwise), Abgrall interface,
   conservation to 1e-12 with periodic boundaries.
 * Seeding (Sec. 3.2): Householder reflection identities, equality with an
-  explicit rotate-reflect-rotate-back, the Riemann variant's S* = v_r.n.
+  explicit rotate-reflect-rotate-back, the Riemann variant's S* = v_r.n; its
+  p* and rho* against linear acoustics for small wall-normal speeds and the
+  exact Riemann solution at moderate ones, its stretch against the
+  kinematics of a uniaxial compression.
 * ELVIRA normal (Sec. 3.3): cut fractions against the closed-form area
   below a line, exact reproduction of straight interfaces (and the seeded
   mirror state of a sharp ramp), convergence on a circle with exact cell
@@ -36,8 +46,9 @@ What pins each part of the oracle (tests marked ``not gpu``):
   elastic wave speed and plastic return invariants.
 
 Parity unpinned: the readings that no external solution distinguishes (the
-HLLC-LM constants, the phi/Vbar star states, the solid HLLC variant, the
-void/wall face modifier) are pinned only by internal identities.
+exact HLLC-LM constants beyond the Ma^2 scaling, the phi star state, the
+solid HLLC variant's star-region flux) are pinned only by internal
+identities.
 """
 from __future__ import annotations
 
@@ -120,6 +131,7 @@ def lib(variant=None):
             L.orc_rigid_force.argtypes = [vp, dp, dp, dp]
             L.orc_conserved_totals.argtypes = [vp, dp]
             L.orc_candidates.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+            L.orc_bvd_select.argtypes = [vp, dp, dp, dp, dp]
             L.orc_prim_to_cons.argtypes = [vp, dp, dp]
             L.orc_cons_to_prim.argtypes = [vp, dp, dp]
             L.orc_thermo.argtypes = [vp, dp, dp]
@@ -288,6 +300,13 @@ class Oracle:
     def candidates(self, qm, q0, qp):
         out = np.zeros(4)
         self._L.orc_candidates(self._h, qm, q0, qp, _dp(out))
+        return out
+
+    def bvd_select(self, cm, c0, cp):
+        """Faces (left, right) BVD selects for a cell from the candidate
+        quadruples of its left neighbour, itself and its right neighbour."""
+        out = np.zeros(2)
+        self._L.orc_bvd_select(self._h, _dp(_arr(cm, 4)), _dp(_arr(c0, 4)), _dp(_arr(cp, 4)), _dp(out))
         return out
 
     def prim_to_cons(self, W):

@@ -1491,6 +1491,12 @@ ORC_API void orc_candidates(void* h, double qm, double q0, double qp, double* ou
   static_cast<Oracle*>(h)->candidates(qm, q0, qp, out4);
 }
 
+// BVD selection of one cell from the candidates of the left neighbour, the
+// cell and the right neighbour (4 values each, as orc_candidates returns).
+ORC_API void orc_bvd_select(void* h, const double* cm, const double* c0, const double* cp, double* out2) {
+  static_cast<Oracle*>(h)->bvd_select(cm, c0, cp, out2[0], out2[1]);
+}
+
 ORC_API void orc_prim_to_cons(void* h, const double* W, double* Uc) { static_cast<Oracle*>(h)->prim_to_cons(W, Uc); }
 ORC_API void orc_cons_to_prim(void* h, const double* Uc, double* W) { static_cast<Oracle*>(h)->cons_to_prim(Uc, W); }
 
