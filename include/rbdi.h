@@ -378,6 +378,25 @@ RBDI_API int rbdi_mlp_forward(rbdi_mlp* m, const float* z, int n, float* y);
  * backward passes (BF16 operands, FP32 accumulation). */
 RBDI_API int rbdi_mlp_grad(rbdi_mlp* m, const float* z, const float* t, int n, float* grad, float* loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid hipMalloc):
+ * the gradient and loss of rbdi_mlp_grad for n device-resident samples, with
+ * nothing allocated. z, t: device, n x 6 FP32 (sample-major); grad: device,
+ * 9158 FP32 (flat layout); loss: device, 1 FP32 -- all caller-owned. The
+ * per-block partial gradients live in a fixed device array of the library
+ * (one row per 64 samples, RBDI_MLP_GRAD_NOALLOC_MAX / 64 rows, 9.4 MB),
+ * which each GPU the library runs on holds until the process ends; its
+ * address is resolved once per device, at rbdi_mlp_create or at the first
+ * call. Enqueued on hip_stream (a hipStream_t as void*, NULL = the null
+ * stream); does not synchronise. Results equal rbdi_mlp_grad's bitwise (same
+ * kernels, same summation order). Every call on one GPU uses that GPU's one
+ * array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. BAD_ARG for null
+ * pointers or n outside [1, RBDI_MLP_GRAD_NOALLOC_MAX]. */
+#define RBDI_MLP_GRAD_NOALLOC_MAX 16384
+RBDI_API int rbdi_mlp_grad_noalloc(rbdi_mlp* m, const float* z, const float* t, int n, float* grad, float* loss,
+                                   void* hip_stream);
+
 /* iters Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr with a
  * cosine decay to zero) on consecutive batches of `batch` samples (a
  * multiple of 64), cycling through the n samples in their given order

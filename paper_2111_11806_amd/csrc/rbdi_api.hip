@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1406,6 +1407,38 @@ RBDI_API int rbdi_batch_autotune(rbdi_batch* b, int reps, rbdi_tuning* best) {
 
 namespace {
 
+// Partial gradient rows of rbdi_mlp_grad_noalloc: one row (kNParam gradients
+// + the loss) per 64-sample block, kNoAllocRows rows, in a fixed device array
+// (9.4 MB) that each GPU the library runs on holds until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// stands for a host-side shadow, not a device address): it uses the address
+// hipGetSymbolAddress returns for the current device, resolved once per
+// device and kept in g_scratch.
+constexpr int kNoAllocRows = RBDI_MLP_GRAD_NOALLOC_MAX / 64;
+static __device__ __align__(256) float scratch[(size_t)kNoAllocRows * (kNParam + 1)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (resolved on the
+// first call on that device).
+int scratch_address(float** out) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RBDI_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RBDI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch[dev];
+  return RBDI_OK;
+}
+
 void mlp_free(rbdi_mlp* m) {
   void* ptrs[] = {m->blob, m->bias, m->master, m->m1, m->m2, m->sum};
   for (void* p : ptrs)
@@ -1445,6 +1478,13 @@ RBDI_API int rbdi_mlp_create(rbdi_mlp** out) {
     mlp_free(m);
     delete m;
     return fail(RBDI_ERR_OOM, std::string("mlp allocation: ") + hipGetErrorString(e));
+  }
+  // set-up of rbdi_mlp_grad_noalloc on this device
+  float* sp = nullptr;
+  if (const int rc = scratch_address(&sp)) {
+    mlp_free(m);
+    delete m;
+    return rc;
   }
   *out = m;
   return RBDI_OK;
@@ -1509,7 +1549,8 @@ RBDI_API int rbdi_mlp_grad(rbdi_mlp* m, const float* z, const float* t, int n, f
   if (!rc) {
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64), 0, nullptr, mlp_dev(m), (const float*)dz, (const float*)dt,
                        0LL, n, n, part);
-    hipLaunchKernelGGL(k_mlp_sum, dim3((kNParam + 256) / 256), dim3(256), 0, nullptr, (const float*)part, nb, m->sum);
+    hipLaunchKernelGGL(k_mlp_sum, dim3((kNParam + 256) / 256), dim3(256), 0, nullptr, (const float*)part, nb, m->sum,
+                       m->sum + kNParam);
     std::vector<float> h(kNParam + 1);
     if (hipMemcpy(h.data(), m->sum, sizeof(float) * (kNParam + 1), hipMemcpyDeviceToHost) != hipSuccess)
       rc = fail(RBDI_ERR_HIP, "mlp_grad copy");
@@ -1523,6 +1564,22 @@ RBDI_API int rbdi_mlp_grad(rbdi_mlp* m, const float* z, const float* t, int n, f
   if (dt) (void)hipFree(dt);
   if (part) (void)hipFree(part);
   return rc;
+}
+
+RBDI_API int rbdi_mlp_grad_noalloc(rbdi_mlp* m, const float* z, const float* t, int n, float* grad, float* loss,
+                                   void* hip_stream) {
+  if (!m || !z || !t || !grad || !loss) return fail(RBDI_ERR_BAD_ARG, "null mlp_grad_noalloc argument");
+  if (n < 1 || n > RBDI_MLP_GRAD_NOALLOC_MAX)
+    return fail(RBDI_ERR_BAD_ARG, "mlp_grad_noalloc: n = " + std::to_string(n) + " outside [1, " +
+                                      std::to_string(RBDI_MLP_GRAD_NOALLOC_MAX) + "]");
+  float* part = nullptr;
+  if (const int rc = scratch_address(&part)) return rc;
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nb = (n + 63) / 64;
+  // every block writes its whole partial row: nothing to clear
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64), 0, st, mlp_dev(m), z, t, 0LL, n, n, part);
+  hipLaunchKernelGGL(k_mlp_sum, dim3((kNParam + 256) / 256), dim3(256), 0, st, (const float*)part, nb, grad, loss);
+  return check_launch();
 }
 
 RBDI_API int rbdi_mlp_train(rbdi_mlp* m, const float* z, const float* t, int n, int batch, int iters, float lr,

@@ -421,12 +421,15 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev m, const float* __restri
 }
 
 // Sum of the per-block partial rows in block order (deterministic).
-__global__ void k_mlp_sum(const float* __restrict__ part, int nblocks, float* __restrict__ out) {
+// Gradients go to grad[0..kNParam), the loss to *loss.
+__global__ void k_mlp_sum(const float* __restrict__ part, int nblocks, float* __restrict__ grad,
+                          float* __restrict__ loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kNParam) return;
   float s = 0.0f;
   for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * (kNParam + 1) + p];
-  out[p] = s;
+  if (p < kNParam) grad[p] = s;
+  else *loss = s;
 }
 
 // Where parameter p lives in the padded BF16 arrays (W and W^T copies).

@@ -74,10 +74,11 @@ EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rb
            "rbdi_batch_create", "rbdi_batch_destroy", "rbdi_batch_set_stream", "rbdi_batch_set_tuning",
            "rbdi_batch_get_tuning", "rbdi_batch_autotune", "rbdi_batch_step", "rbdi_batch_advance",
            "rbdi_mlp_create", "rbdi_mlp_destroy", "rbdi_mlp_set_params", "rbdi_mlp_get_params", "rbdi_mlp_data",
-           "rbdi_mlp_forward", "rbdi_mlp_grad", "rbdi_mlp_train", "rbdi_set_surrogate"]
+           "rbdi_mlp_forward", "rbdi_mlp_grad", "rbdi_mlp_grad_noalloc", "rbdi_mlp_train", "rbdi_set_surrogate"]
 NUM_KCLASS = 7
 KCLASS = ["sweep_x", "sweep_y", "sweep_z", "seed", "band", "cfl_dt", "sources_mlp"]
 N_MLP_PARAMS = 9158
+MLP_GRAD_NOALLOC_MAX = 16384  # RBDI_MLP_GRAD_NOALLOC_MAX
 
 
 def lib_path():
@@ -134,6 +135,7 @@ def load():
     L.rbdi_mlp_data.argtypes = [dp, ip, ctypes.c_double, fp, fp]
     L.rbdi_mlp_forward.argtypes = [vp, fp, ip, fp]
     L.rbdi_mlp_grad.argtypes = [vp, fp, fp, ip, fp, fp]
+    L.rbdi_mlp_grad_noalloc.argtypes = [vp, vp, vp, ip, vp, vp, vp]
     L.rbdi_mlp_train.argtypes = [vp, fp, fp, ip, ip, ip, ctypes.c_float, fp]
     L.rbdi_set_surrogate.argtypes = [vp, vp]
     _lib = L
@@ -499,6 +501,22 @@ class Mlp:
         loss = ctypes.c_float()
         _check(load().rbdi_mlp_grad(self._m, _fp(z), _fp(t), z.shape[0], _fp(g), ctypes.byref(loss)))
         return g, loss.value
+
+    def grad_noalloc(self, z, t, grad, loss, stream=None):
+        """rbdi_mlp_grad_noalloc on device tensors: z, t (n x 6 float32),
+        grad (9158 float32) and loss (1 float32), all contiguous on the
+        network's GPU; enqueued on stream (a torch stream, None = the null
+        stream), no synchronisation."""
+        for name, a, n in (("z", z, None), ("t", t, None), ("grad", grad, N_MLP_PARAMS), ("loss", loss, 1)):
+            if not (a.is_cuda and a.dtype.is_floating_point and a.element_size() == 4 and a.is_contiguous()):
+                raise ValueError(f"{name}: a contiguous float32 device tensor is required")
+            if n is not None and a.numel() != n:
+                raise ValueError(f"{name}: expected {n} values, got {a.numel()}")
+        if z.numel() % 6 or z.numel() != t.numel():
+            raise ValueError("z and t must both be n x 6")
+        sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(load().rbdi_mlp_grad_noalloc(self._m, z.data_ptr(), t.data_ptr(), z.numel() // 6, grad.data_ptr(),
+                                            loss.data_ptr(), sp))
 
     def train(self, z, t, batch=4096, iters=1000, lr=1e-3):
         z = _f32(z).reshape(-1, 6)
