@@ -524,6 +524,10 @@ RBDI_API int rbdi_set_material(rbdi_handle* h, int l, const rbdi_eos* e) {
     m.alpha = e->alpha;
     m.beta = e->beta;
     m.kc = e->K0 / (2.0 * e->alpha * e->alpha);
+    // small integer exponents are evaluated by multiplication on the device
+    m.ialpha = (e->alpha == std::floor(e->alpha) && e->alpha >= 1.0 && e->alpha <= 8.0) ? (int)e->alpha : 0;
+    const double b1 = e->beta + 1.0;
+    m.ibeta1 = (b1 == std::floor(b1) && b1 >= 1.0 && b1 <= 8.0) ? (int)b1 : 0;
     m.Gam = e->Gamma0;
     m.invGam = 1.0 / e->Gamma0;
     m.sigY = e->sigma_y;

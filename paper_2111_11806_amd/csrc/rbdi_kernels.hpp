@@ -136,6 +136,16 @@ __device__ inline double shdn(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Keeps a value's computation where it stands in the program: an empty asm
+// that reads and writes the register. Without it the compiler sinks every
+// field's BVD selection to the end of the unrolled per-field loop, so all
+// fields' candidates and shifted neighbour faces stay live at once (18
+// fields: 256 registers and 74 spilled per lane, against 126 with it).
+template <typename T>
+__device__ inline void pin(T& x) {
+  asm volatile("" : "+v"(x));
+}
+
 __device__ inline long long cell_index(const Params& P, int i, int j, int k) {
   return (long long)i * P.st[0] + (long long)j * P.st[1] + (long long)k * P.st[2];
 }
@@ -306,6 +316,87 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
   d[S::R] = ((rfl - rflm) - W[S::R] * (vf - vfm)) * inv;
 }
 
+// sweep_core for the elastoplastic system, with the same results: the face
+// solver's wave data are built once, then each field's flux, its difference
+// with the left neighbour's and its non-conservative terms are formed one
+// field at a time and handed to put(q, d_q) (all lanes call put; only lanes
+// 3..60 carry a complete d). The flux and update arrays of sweep_core are
+// never held in registers, which keeps these 18-field sweeps within two
+// wavefronts' register budget per SIMD.
+template <class S, typename T, int DIR, class Put>
+__device__ inline void sweep_core_streamed(const Params& P, const T* W, int pos, const int* pc, double tc, Put&& put) {
+  constexpr bool Z = false;
+  T sL[S::NF], sR[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) {
+    if (q == S::R && P.r_static) { sL[q] = W[q]; sR[q] = W[q]; continue; }
+    const T wm = shup<Z>(W[q]), wp = shdn<Z>(W[q]);
+    const Cand<T> c = candidates(P, wm, W[q], wp);
+    const T lmR = shup<Z>(c.mR), ltR = shup<Z>(c.tR);
+    const T rmL = shdn<Z>(c.mL), rtL = shdn<Z>(c.tL);
+    bvd(P, lmR, ltR, c, rmL, rtL, sL[q], sR[q]);
+    pin(sL[q]);
+    pin(sR[q]);
+  }
+  const bool bad = !admissible<S>(P, sL) || !admissible<S>(P, sR);
+  if (__any(bad)) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) {
+      sL[q] = bad ? W[q] : sL[q];
+      sR[q] = bad ? W[q] : sR[q];
+    }
+  }
+  T WR[S::NF];
+#pragma unroll
+  for (int q = 0; q < S::NF; ++q) WR[q] = shdn<Z>(sL[q]);
+  HllcFace<S, DIR, T> face;
+  face.init(P, sR, WR);
+  const T us = (T)face.ustar();
+  T Vs[3] = {T(0), T(0), T(0)};
+  if constexpr (S::S) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Vs[b] = (T)face.vstar(sR, WR, b);
+  }
+  T vf = T(0), rfl = T(0);
+  if (!P.r_static) {
+    double xf[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xf[a] = (a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0) - P.vr[a] * tc;
+    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR] - P.vr[DIR] * tc;
+    double v[3];
+    rigid_velocity(P, xf, v);
+    vf = (T)v[DIR];
+    rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
+  }
+  const T inv = (T)P.inv_dx[DIR];
+  const T du = us - shup<Z>(us);
+  T dV[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) dV[b] = Vs[b] - shup<Z>(Vs[b]);
+  double Bm = 0.0;
+  if (P.stiff) {
+    double phi[kMaxMat], rl[kMaxMat];
+    phases_w<S>(W, phi, rl);
+    Bm = mix_B<S>(P, phi);
+  }
+#pragma unroll
+  for (int q = 0; q < S::NT; ++q) {
+    const T F = (T)face.flux(sR, WR, q);
+    T d = (F - shup<Z>(F)) * inv;
+    if (q >= S::cPHI(0) && q < S::cPHI(0) + S::N - 1) d -= W[S::wPHI(q - S::cPHI(0))] * du * inv;
+    if (q == S::cE && P.stiff) d += (T)(Bm * (double)(du * inv));
+    if constexpr (S::S) {
+      if (q >= S::cV(0, 0) && q < S::cEP) {
+        const int a = (q - S::cV(0, 0)) / 3, b = (q - S::cV(0, 0)) % 3;
+        const T ua = a < S::D ? W[S::wU(a)] : T(0);
+        d -= (T(2.0 / 3.0) * W[S::wV(a, b)] * du - ua * dV[b]) * inv;
+      }
+    }
+    put(q, d);
+  }
+  put(S::R, ((rfl - shup<Z>(rfl)) - W[S::R] * (vf - shup<Z>(vf))) * inv);
+}
+
 // Mirror / Dirichlet treatment of a primitive loaded for a ghost position.
 template <class S, typename T, int DIR>
 __device__ inline void ghost_fix(const Params& P, int mode, int face, T* W) {
@@ -336,7 +427,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
                                              const T* __restrict__ Dacc, T* __restrict__ Uout,
                                              DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                              const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
-                                             long long blin, int wpb, int nparts) {
+                                             long long blin, int wpb, int nparts, T* xlds = nullptr) {
   const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
   const int lane = threadIdx.x & (kWave - 1);
@@ -366,7 +457,16 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     ghost_fix<S, T, 0>(P, mode, face, W);
   }
   T d[S::NF];
-  sweep_core<S, T, 0>(P, W, pos, pc, tc, d);
+  if constexpr (S::S) {
+    // streamed: this lane's d goes through its own LDS slots (no other lane
+    // reads them); U_in is reloaded for the combine instead of being held
+    T* my = xlds + (size_t)wave * S::NF * kWave + lane;
+    sweep_core_streamed<S, T, 0>(P, W, pos, pc, tc, [&](int q, T v) { my[q * kWave] = v; });
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) d[q] = my[q * kWave];
+  } else {
+    sweep_core<S, T, 0>(P, W, pos, pc, tc, d);
+  }
   if (A.rhs_only & 2) {
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) d[q] = T(0);
@@ -396,7 +496,8 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     T Un[S::NF];
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) {
-      const T ui = Uc[q];  // an output lane is an interior cell: its own load
+      // an output lane is an interior cell: U_in is its own load
+      const T ui = S::S ? Uin[q * P.fs + c] : Uc[q];
       const T ust = ui - dtt * d[q];
       if (stage == 0) {
         Un[q] = (rigid && q != S::R) ? ui : ust;
@@ -438,9 +539,9 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
 // spills, beats five with spills and six; the LDS tile holds the y/z sweeps
 // at three). Other systems: the compiler's choice (1 = no request).
 template <class S>
-constexpr int x_sweep_waves() { return (S::S || S::N != 1) ? 1 : 4; }
+constexpr int x_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 4; }
 template <class S>
-constexpr int tile_sweep_waves() { return (S::S || S::N != 1) ? 1 : 3; }
+constexpr int tile_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 3; }
 
 template <class S, typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
@@ -450,8 +551,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
   const int wpb = blockDim.x / kWave;
   const long long blin = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
-  sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
-                     blin, wpb, nparts);
+  if constexpr (S::S) {
+    __shared__ T xlds[kMaxWPB * S::NF * kWave];
+    sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
+                       blin, wpb, nparts, xlds);
+  } else {
+    sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
+                       blin, wpb, nparts);
+  }
 }
 
 // Sweeps along y and z (not final): a block stages a tile of kTC columns x
@@ -526,6 +633,9 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const double tc = sc->t[A.par] - sc->t_motion;
+  // one column at a time (unrolled, two columns' sweeps would interleave and
+  // double the register demand)
+#pragma unroll 1
   for (int c = wave; c < TC; c += kTileThreads / kWave) {
     const int x = x0 + c;
     if (x >= P.n[0]) break;  // uniform in the wavefront
@@ -543,15 +653,27 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
       cons_to_prim<S>(P, Uc, W);
     }
     ghost_fix<S, T, DIR>(P, mode, face, W);
-    T d[S::NF];
-    sweep_core<S, T, DIR>(P, W, pos, pc, tc, d);
-    if (A.rhs_only & (2 << DIR)) {
+    const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
+    const bool zero = (A.rhs_only & (2 << DIR)) != 0;
+    if constexpr (S::S) {
+      // streamed: each field's d goes straight into this lane's slot of the
+      // tile column (its U_in there was consumed by the closure above; the
+      // slots of halo lanes and of positions beyond the domain are written
+      // too, and never read: the store below takes the output rows only)
+      sweep_core_streamed<S, T, DIR>(P, W, pos, pc, tc, [&](int q, T v) {
+        tile[(q * TC + c) * kRS + lane] = zero ? T(0) : v;
+      });
+    } else {
+      T d[S::NF];
+      sweep_core<S, T, DIR>(P, W, pos, pc, tc, d);
+      if (zero) {
 #pragma unroll
-      for (int q = 0; q < S::NF; ++q) d[q] = T(0);
-    }
-    if (lane >= kHalo && lane < kHalo + kOut && pos < nd) {
+        for (int q = 0; q < S::NF; ++q) d[q] = T(0);
+      }
+      if (outlane) {
 #pragma unroll
-      for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + lane] = d[q];
+        for (int q = 0; q < S::NF; ++q) tile[(q * TC + c) * kRS + lane] = d[q];
+      }
     }
   }
   __syncthreads();

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void k_sources_mlp(Params P, T* __restrict__ U
 #pragma unroll
       for (int q = 0; q < 9; ++q) V[q] = Vn[q];
       const int sp = P.solid_phase;
-      const double as = phi[sp] * rl[sp];
+      const double as = pick<S::N>(phi, sp) * pick<S::N>(rl, sp);
       Uc[S::cEP] = (T)((double)Uc[S::cEP] + as * 0.816496580927726 * (1.0 - s) * Hn);
     }
   }

@@ -42,6 +42,7 @@ struct MatDev {
   double Gam, invGam;   // Gruneisen coefficient and its inverse
   double Bfl;           // fluids: rho e_ref - p_ref / Gamma = gamma p_inf / Gamma
   double rho0, invrho0, K0, G0, alpha, beta, kc;  // Romenskii, kc = K0 / (2 alpha^2)
+  int ialpha, ibeta1;   // alpha and beta + 1 when they are integers in [1, 8], else 0
   double sigY;
   double gGam;          // fluids: gamma / Gamma (sound-speed weight)
 };
@@ -96,6 +97,17 @@ struct Sys {
   __host__ __device__ static constexpr int wV(int a, int b) { return 2 * N + D + 3 * a + b; }
   static constexpr int wEP = 2 * N + D + 9;
 };
+
+// Element k of a small per-thread array, k known only at run time (the
+// solid phase), by a chain of selects: indexing such an array with a run-time
+// value would place the whole array in scratch memory.
+template <int N, typename T>
+__device__ inline T pick(const T* a, int k) {
+  T v = a[0];
+#pragma unroll
+  for (int l = 1; l < N; ++l) v = (k == l) ? a[l] : v;
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // Small 3x3 algebra (stretch tensor)
@@ -205,7 +217,7 @@ __device__ inline double log_w(int k) { return (k & 1 ? 0.5 : -0.5) / (double)k;
 // Hencky strain H = (1/2) ln(Vbar Vbar^T) (equals ln Vbar for a symmetric
 // stretch; Sec. 2.1.2) and J2 = H:H, by eigen-decomposition.
 template <typename T>
-__device__ __attribute__((noinline)) void hencky3_eig(const T V[9], T H[9], T& J2) {
+__device__ __forceinline__ void hencky3_eig(const T V[9], T H[9], T& J2) {
   T b[3][3], Q[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -270,11 +282,19 @@ struct PhaseOut {
   double B, c2, G;
 };
 
+// x^k for 1 <= k <= 8 by repeated multiplication (k = 0: pow(x, e)).
+__device__ inline double pow_small(double x, int k, double e) {
+  if (k == 0) return pow(x, e);
+  double r = x;
+  for (int i = 1; i < k; ++i) r *= x;
+  return r;
+}
+
 __device__ inline void romenskii_ref(const MatDev& m, double rho, double J2, double& rhoe_ref,
                                      double& p_ref, double& dpref, double& G) {
   const double x = rho * m.invrho0;
-  const double y = (m.alpha == 1.0) ? x : pow(x, m.alpha);
-  G = m.G0 * pow(x, m.beta + 1.0);
+  const double y = pow_small(x, m.ialpha, m.alpha);
+  G = m.G0 * pow_small(x, m.ibeta1, m.beta + 1.0);
   const double ym = y - 1.0;
   rhoe_ref = m.kc * ym * ym + G * J2;
   p_ref = m.kc * ym * ((2.0 * m.alpha - 1.0) * y + 1.0) + m.beta * G * J2;
@@ -398,6 +418,46 @@ __device__ inline void mix_c2_G(const Params& P, const double* phi, const double
   sigY = nY * inv;
 }
 
+// Face-state thermodynamics in one pass over the phases (one Romenskii
+// reference-curve evaluation per phase): mixture c^2, shear modulus, yield
+// stress (as mix_c2_G) and rho e from p (as mix_rhoe).
+template <class S>
+__device__ inline void mix_state(const Params& P, const double* phi, const double* rho, double J2, double p,
+                                 double& c2, double& G, double& sigY, double& rhoe) {
+  if constexpr (!S::S) {
+    mix_c2_G<S>(P, phi, rho, J2, p, c2, G, sigY);
+    rhoe = mix_rhoe<S>(P, phi, rho, J2, p);
+    return;
+  }
+  double rhom = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) rhom += phi[l] * rho[l];
+  double nc = 0.0, nG = 0.0, nY = 0.0, den = 0.0, s = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const MatDev& m = P.mat[l];
+    double cl2, Gl = 0.0;
+    const double ir = frcp(rho[l]);
+    if (m.kind == EOS_ROMENSKII) {
+      double er, pr, dp;
+      romenskii_ref(m, rho[l], J2, er, pr, dp, Gl);
+      cl2 = ((m.Gam + 1.0) * (p - pr) + (4.0 / 3.0) * Gl) * ir + dp;
+      s += phi[l] * (er - pr * m.invGam);
+    } else {
+      cl2 = m.gamma * (p + m.pinf) * ir;
+    }
+    nc += phi[l] * rho[l] * cl2 * m.invGam;
+    nG += phi[l] * Gl * m.invGam;
+    nY += phi[l] * m.sigY * m.invGam;
+    den += phi[l] * m.invGam;
+  }
+  const double inv = frcp(den);
+  c2 = nc * frcp(rhom) * inv;
+  G = nG * inv;
+  sigY = nY * inv;
+  rhoe = p * den + s;
+}
+
 // Volume fractions and phasic densities of a primitive vector.
 template <class S, typename T>
 __device__ inline void phases_w(const T* W, double* phi, double* rho) {
@@ -458,7 +518,7 @@ __device__ inline void cons_to_prim(const Params& P, const T* U, T* W, double* H
       for (int q = 0; q < 9; ++q) Hout[q] = H[q];
     }
     const int sp = P.solid_phase;
-    W[S::wEP] = (T)((double)U[S::cEP] / (double)U[S::cA(sp)]);
+    W[S::wEP] = (T)((double)U[S::cEP] / (double)pick<S::N>(U + S::cA(0), sp));
   }
   if (J2out) *J2out = J2;
 #pragma unroll
@@ -502,7 +562,7 @@ __device__ inline void prim_to_cons(const Params& P, const T* W, T* U, double* H
       for (int q = 0; q < 9; ++q) Hout[q] = H[q];
     }
     const int sp = P.solid_phase;
-    U[S::cEP] = (T)(phi[sp] * rl[sp] * (double)W[S::wEP]);
+    U[S::cEP] = (T)(pick<S::N>(phi, sp) * pick<S::N>(rl, sp) * (double)W[S::wEP]);
   }
   U[S::cE] = (T)(mix_rhoe<S>(P, phi, rl, J2, (double)W[S::wP]) + 0.5 * ke);
 #pragma unroll
@@ -627,8 +687,8 @@ __device__ inline void side_state(const Params& P, const T* W, SideState<S>& s) 
     for (int q = 0; q < 9; ++q) V[q] = (double)W[S::wV(0, 0) + q];
     hencky3(V, s.H, J2);
   }
-  double c2, G, sY;
-  mix_c2_G<S>(P, s.phi, s.rl, J2, p, c2, G, sY);
+  double c2, G, sY, rhoe;
+  mix_state<S>(P, s.phi, s.rl, J2, p, c2, G, sY, rhoe);
   s.c = sqrt(c2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -637,7 +697,7 @@ __device__ inline void side_state(const Params& P, const T* W, SideState<S>& s) 
     s.sig[a] = sg;
   }
   s.P = -s.sig[DIR];
-  s.E = mix_rhoe<S>(P, s.phi, s.rl, J2, p) + 0.5 * s.rho * ke;
+  s.E = rhoe + 0.5 * s.rho * ke;
 }
 
 // Conserved value, physical flux and star value of field q on one side.
@@ -676,7 +736,7 @@ __device__ inline void field_terms(const T* W, const SideState<S>& s, int q, int
     f = u * un - (double)W[S::wV(DIR, b)] * s.u[a];
     us = (a == DIR ? cn : ct) * u;
   } else {  // phi_s rho_s eps_p
-    u = s.phi[sp] * s.rl[sp] * (double)W[S::wEP];
+    u = pick<S::N>(s.phi, sp) * pick<S::N>(s.rl, sp) * (double)W[S::wEP];
     f = u * un;
     us = chi * u;
   }
@@ -781,6 +841,77 @@ __device__ inline void hllc(const Params& P, const T* WL, const T* WR, T* F, T& 
   if (SL >= 0.0 || Ss >= 0.0) toro_side<S, DIR>(WL, L, sp, SL, Ss, !(SL >= 0.0), F, ustar, Vstar);
   else toro_side<S, DIR>(WR, R, sp, SR, Ss, SR > 0.0, F, ustar, Vstar);
 }
+
+// The same HLLC / HLLC-LM face in a form that yields one field's flux at a
+// time: init() builds both side states and the wave data (speeds, S*, chi,
+// the LM factor and which part of the fan holds x/t = 0); flux(q), ustar()
+// and vstar() then give what hllc() gives, with the same arithmetic, without
+// a flux array held in registers. Used by the sweeps of the elastoplastic
+// system, whose 18 fields otherwise need more registers than a wavefront
+// can hold without spilling.
+enum { FAN_LEFT = 0, FAN_RIGHT = 1, FAN_CENTRAL = 2, FAN_STAR_L = 3, FAN_STAR_R = 4 };
+
+template <class S, int DIR, typename T>
+struct HllcFace {
+  SideState<S> L, R;
+  double SL, SR, Ss, chiL, chiR, cnL, ctL, cnR, ctR, ph, aS;
+  int mode, sp;
+
+  __device__ inline void init(const Params& P, const T* WL, const T* WR) {
+    side_state<S, DIR>(P, WL, L);
+    side_state<S, DIR>(P, WR, R);
+    SL = fmin(L.un - L.c, R.un - R.c);
+    SR = fmax(L.un + L.c, R.un + R.c);
+    const double mL = L.rho * (SL - L.un), mR = R.rho * (SR - R.un);
+    Ss = (R.P - L.P + L.un * mL - R.un * mR) * frcp(mL - mR);
+    sp = P.solid_phase < 0 ? 0 : P.solid_phase;
+    if ((P.riemann == RS_HLLC_LM || S::S) && SL < 0.0 && SR > 0.0) mode = FAN_CENTRAL;
+    else if (SL >= 0.0) mode = FAN_LEFT;
+    else if (Ss >= 0.0) mode = FAN_STAR_L;
+    else if (SR > 0.0) mode = FAN_STAR_R;
+    else mode = FAN_RIGHT;
+    chiL = (SL - L.un) * frcp(SL - Ss);
+    chiR = (SR - R.un) * frcp(SR - Ss);
+    cnL = ctL = cnR = ctR = 1.0;
+    if constexpr (S::S) {
+      ctL = cbrt(chiL); cnL = 1.0 / (ctL * ctL);
+      ctR = cbrt(chiR); cnR = 1.0 / (ctR * ctR);
+    }
+    ph = 1.0;
+    if (mode == FAN_CENTRAL && P.riemann == RS_HLLC_LM &&
+        !(fabs(L.un) >= P.lm_mach * L.c || fabs(R.un) >= P.lm_mach * R.c)) {
+      const double Ma = fmax(fabs(L.un) * frcp(L.c), fabs(R.un) * frcp(R.c));
+      ph = sin_quadrant(fmin(1.0, Ma / P.lm_mach) * (M_PI * 0.5));
+    }
+    aS = fabs(Ss);
+  }
+
+  // flux of thermodynamic field q
+  __device__ inline double flux(const T* WL, const T* WR, int q) const {
+    double uL, fL, usL, uR, fR, usR;
+    field_terms<S, DIR>(WL, L, q, sp, SL, Ss, chiL, cnL, ctL, uL, fL, usL);
+    field_terms<S, DIR>(WR, R, q, sp, SR, Ss, chiR, cnR, ctR, uR, fR, usR);
+    const double fc = 0.5 * (fL + fR) + 0.5 * (ph * SL * (usL - uL) + aS * (usL - usR) + ph * SR * (usR - uR));
+    const double fsl = fL + SL * (usL - uL), fsr = fR + SR * (usR - uR);
+    return mode == FAN_CENTRAL ? fc : mode == FAN_LEFT ? fL : mode == FAN_RIGHT ? fR : mode == FAN_STAR_L ? fsl : fsr;
+  }
+
+  // wall velocity (the flux formula applied to the unit field)
+  __device__ inline double ustar() const {
+    const double uc = 0.5 * (L.un + R.un) + 0.5 * (ph * SL * (chiL - 1.0) + aS * (chiL - chiR) + ph * SR * (chiR - 1.0));
+    return mode == FAN_CENTRAL ? uc : mode == FAN_LEFT ? L.un : mode == FAN_RIGHT ? R.un
+         : mode == FAN_STAR_L ? L.un + SL * (chiL - 1.0) : R.un + SR * (chiR - 1.0);
+  }
+
+  // wall stretch row Vbar*_{DIR,b}
+  __device__ inline double vstar(const T* WL, const T* WR, int b) const {
+    const double vl = (double)WL[S::wV(DIR, b)], vr = (double)WR[S::wV(DIR, b)];
+    const double w = (Ss - SL) * frcp(SR - SL);
+    const double vc = vr * cnR + w * (vl * cnL - vr * cnR);
+    return mode == FAN_CENTRAL ? vc : mode == FAN_LEFT ? vl : mode == FAN_RIGHT ? vr
+         : mode == FAN_STAR_L ? vl * cnL : vr * cnR;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Rigid-body velocity and seeding states (Sec. 2.3, Sec. 3.2)
@@ -902,7 +1033,7 @@ __device__ inline double exp_w(int k) {
 }
 
 // E = exp(a H) for symmetric H: by eigen-decomposition.
-__device__ __attribute__((noinline)) void plastic_exp_eig(double a, const double* H, double* E) {
+__device__ __forceinline__ void plastic_exp_eig(double a, const double* H, double* E) {
   double A[3][3], Q[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) A[i][j] = a * H[3 * i + j];
@@ -972,7 +1103,7 @@ __device__ inline void solid_sources(const Params& P, T* U) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) V[q] = Vn[q];
       const int sp = P.solid_phase;
-      const double as = phi[sp] * rl[sp];
+      const double as = pick<S::N>(phi, sp) * pick<S::N>(rl, sp);
       U[S::cEP] = (T)((double)U[S::cEP] + as * 0.816496580927726 * (1.0 - s) * Hn);
     }
   }
