@@ -56,6 +56,7 @@ import ctypes
 import os
 import subprocess
 import threading
+import time
 
 import numpy as np
 
@@ -120,6 +121,7 @@ def lib(variant=None):
                 getattr(L, nm).argtypes = [vp, dp]
             L.orc_set_rigid_sdf.argtypes = [vp, dp, ctypes.c_double, dp, dp, dp]
             L.orc_set_rigid_motion.argtypes = [vp, dp, dp, dp]
+            L.orc_set_rigid_bodies.argtypes = [vp, ip, dp, dp, dp, dp, dp]
             L.orc_compute_dt.restype = ctypes.c_double
             L.orc_compute_dt.argtypes = [vp, ctypes.c_double]
             L.orc_step.argtypes = [vp, ctypes.c_double]
@@ -132,6 +134,8 @@ def lib(variant=None):
             L.orc_conserved_totals.argtypes = [vp, dp]
             L.orc_candidates.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
             L.orc_bvd_select.argtypes = [vp, dp, dp, dp, dp]
+            L.orc_set_threads.argtypes = [ip]
+            L.orc_get_threads.restype = ip
             L.orc_prim_to_cons.argtypes = [vp, dp, dp]
             L.orc_cons_to_prim.argtypes = [vp, dp, dp]
             L.orc_thermo.argtypes = [vp, dp, dp]
@@ -159,6 +163,15 @@ def _arr(x, n=None):
     if n is not None:
         assert a.size == n, (a.size, n)
     return a
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (for timing the CPU baseline)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def material_params(m) -> np.ndarray:
@@ -207,6 +220,8 @@ class Oracle:
         self.set_state_prim(prob.W0)
         if prob.sdf is not None:
             self.set_rigid_sdf(prob.sdf, prob.width, prob.v_r, prob.omega, prob.center)
+        if prob.bodies:
+            self.set_rigid_bodies(*prob.body_table())
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -243,6 +258,16 @@ class Oracle:
     def set_rigid_motion(self, v, omega, center):
         self._L.orc_set_rigid_motion(self._h, _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3)))
 
+    def set_rigid_bodies(self, v, omega, center, box_lo, box_hi):
+        """Motions of several bodies (rows: body 0 = every point no other
+        body owns, bodies 1.. with ownership boxes [box_lo, box_hi))."""
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+        nb = v.shape[0]
+        a = [np.ascontiguousarray(x, dtype=np.float64).reshape(nb, 3) for x in (v, omega, center, box_lo, box_hi)]
+        rc = self._L.orc_set_rigid_bodies(self._h, nb, *[_dp(x) for x in a])
+        if rc != 0:
+            raise ValueError("orc_set_rigid_bodies: nbody must be 1..4")
+
     def compute_dt(self, cfl):
         return self._L.orc_compute_dt(self._h, float(cfl))
 
@@ -278,13 +303,21 @@ class Oracle:
         self._L.orc_conserved_totals(self._h, _dp(out))
         return out[: self.nf], out[self.nf:]
 
-    def run(self, t_end=None, cfl=None, nsteps=None, dts=None):
-        """Advance with the CFL step (clipped to t_end) and return the dt list."""
+    def run(self, t_end=None, cfl=None, nsteps=None, dts=None, progress=None):
+        """Advance with the CFL step (clipped to t_end) and return the dt list.
+        progress: optional callable(steps done, t), called about every 30 s."""
         out = []
+        last = [time.perf_counter()]
+
+        def tick():
+            if progress is not None and time.perf_counter() - last[0] > 30.0:
+                last[0] = time.perf_counter()
+                progress(len(out), self.t)
         if dts is not None:
             for dt in dts:
                 self.step(dt)
                 out.append(dt)
+                tick()
             return out
         cfl = self.prob.cfl if cfl is None else cfl
         t_end = self.prob.t_end if t_end is None else t_end
@@ -294,6 +327,7 @@ class Oracle:
             self.step(dt)
             out.append(dt)
             k += 1
+            tick()
         return out
 
     # ---- unit-level access used by the pins ----

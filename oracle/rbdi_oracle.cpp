@@ -16,6 +16,7 @@
 //
 // Build: g++ -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
 
+#include <omp.h>
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -29,6 +30,7 @@
 namespace {
 
 constexpr int kMaxMat = 3;
+constexpr int kMaxBodies = 4;  // rigid bodies with their own motion
 constexpr int kMaxF = 32;
 
 enum { EOS_IDEAL = 0, EOS_STIFFENED = 1, EOS_ROMENSKII = 2 };
@@ -243,7 +245,12 @@ struct Oracle {
   double lm_mach = 0.1;
   int nmat = 1, solid_phase = -1;
   Material mat[kMaxMat];
-  double vr[3] = {0, 0, 0}, om[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
+  // Rigid motions: body 0 moves every point no other body claims; body
+  // k >= 1 claims the points of its ownership box [lo, hi). Centres and boxes
+  // are those of the start of the current step.
+  int nbody = 1;
+  double vr[kMaxBodies][3] = {}, om[kMaxBodies][3] = {}, ctr[kMaxBodies][3] = {};
+  double box_lo[kMaxBodies][3] = {}, box_hi[kMaxBodies][3] = {};
   double t = 0;
   size_t ncell = 0;   // cells including ghosts
   std::vector<double> U;  // [L.n][ncell]
@@ -417,12 +424,26 @@ struct Oracle {
   }
 
   // Rigid-body velocity field v_r(x) = v + omega x (x - c), imposed and
-  // one-way (Sec. 2.3). Reading: the centre is taken at the start of the step.
+  // one-way (Sec. 2.3), of the body that owns x. Reading: the centre is taken
+  // at the start of the step.
+  int owner(const double x[3]) const {
+    for (int k = 1; k < nbody; ++k) {
+      bool in = true;
+      for (int a = 0; a < 3; ++a) in = in && x[a] >= box_lo[k][a] && x[a] < box_hi[k][a];
+      if (in) return k;
+    }
+    return 0;
+  }
   void rigid_velocity(const double x[3], double v[3]) const {
-    const double d[3] = {x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2]};
-    v[0] = vr[0] + om[1] * d[2] - om[2] * d[1];
-    v[1] = vr[1] + om[2] * d[0] - om[0] * d[2];
-    v[2] = vr[2] + om[0] * d[1] - om[1] * d[0];
+    const int k = owner(x);
+    const double d[3] = {x[0] - ctr[k][0], x[1] - ctr[k][1], x[2] - ctr[k][2]};
+    v[0] = vr[k][0] + om[k][1] * d[2] - om[k][2] * d[1];
+    v[1] = vr[k][1] + om[k][2] * d[0] - om[k][0] * d[2];
+    v[2] = vr[k][2] + om[k][0] * d[1] - om[k][1] * d[0];
+  }
+  void set_one_body(const double* v, const double* omega, const double* center) {
+    nbody = 1;
+    for (int a = 0; a < 3; ++a) { vr[0][a] = v[a]; om[0][a] = omega[a]; ctr[0][a] = center[a]; }
   }
 
   // ---- ghost cells ---------------------------------------------------------
@@ -1027,7 +1048,12 @@ struct Oracle {
   //     fixed 1.5 dx probe); a probe point is valid when every enclosing cell
   //     centre that carries a nonzero interpolation weight is an interior cell
   //     with r <= 0.5; the first valid point is used; primitive variables are
-  //     interpolated multilinearly; no valid point -> no action;
+  //     interpolated multilinearly; no valid point -> no action. A point in
+  //     the half cell between the outermost cell centres and a domain face
+  //     takes, along that axis, the outermost centre's coordinate (the
+  //     boundary cell's state extends to the face): without it a probe that
+  //     runs along a wall through the first row of centres would flip
+  //     between valid and invalid with the sign of a rounding error;
   //  3-4. mirror state (mirror_state);
   //  5. original: the mirror state replaces the cell state; Riemann: the HLLC
   //     right star state of (mirror, interpolated) replaces it.
@@ -1062,7 +1088,9 @@ struct Oracle {
         int lo[3] = {0, 0, 0};
         double w[3] = {0, 0, 0};
         for (int a = 0; a < dim; ++a) {
-          const double xi = pos[a] + dist * nrm[a] * (dmin / dx[a]);
+          double xi = pos[a] + dist * nrm[a] * (dmin / dx[a]);
+          if (xi < 0.0 && xi >= -0.5) xi = 0.0;
+          if (xi > n[a] - 1 && xi <= n[a] - 0.5) xi = n[a] - 1;
           lo[a] = (int)std::floor(xi);
           w[a] = xi - lo[a];
         }
@@ -1233,6 +1261,10 @@ struct orc_desc {
 
 ORC_API const char* orc_last_error() { return g_err.c_str(); }
 
+// Number of OpenMP threads of the oracle's loops (timing of the baseline).
+ORC_API void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+ORC_API int orc_get_threads() { return omp_get_max_threads(); }
+
 ORC_API void* orc_create(const orc_desc* d) {
   if (!d || d->dim < 1 || d->dim > 3 || d->nmat < 1 || d->nmat > kMaxMat) { g_err = "bad desc"; return nullptr; }
   Oracle* o = new Oracle();
@@ -1357,13 +1389,32 @@ ORC_API int orc_set_rigid_sdf(void* h, const double* sdf, double width, const do
     const int k = (int)(lin / ((size_t)o->n[0] * o->n[1]));
     r[o->idx(i, j, k)] = 0.5 * (1.0 - std::tanh(sdf[lin] / (width * dmin)));
   }
-  for (int a = 0; a < 3; ++a) { o->vr[a] = v[a]; o->om[a] = omega[a]; o->ctr[a] = center[a]; }
+  o->set_one_body(v, omega, center);
   return 0;
 }
 
 ORC_API int orc_set_rigid_motion(void* h, const double* v, const double* omega, const double* center) {
+  static_cast<Oracle*>(h)->set_one_body(v, omega, center);
+  return 0;
+}
+
+// Several rigid bodies in one r field (the extrusion test of Sec. 4.5: a
+// moving piston and a static wedge): nbody x 3 motions, and for bodies
+// 1..nbody-1 their ownership boxes [lo, hi) (row 0 unused). Returns -1 for
+// nbody outside 1..kMaxBodies.
+ORC_API int orc_set_rigid_bodies(void* h, int nbody, const double* v, const double* omega, const double* center,
+                                 const double* lo, const double* hi) {
   Oracle* o = static_cast<Oracle*>(h);
-  for (int a = 0; a < 3; ++a) { o->vr[a] = v[a]; o->om[a] = omega[a]; o->ctr[a] = center[a]; }
+  if (nbody < 1 || nbody > kMaxBodies) return -1;
+  o->nbody = nbody;
+  for (int k = 0; k < nbody; ++k)
+    for (int a = 0; a < 3; ++a) {
+      o->vr[k][a] = v[3 * k + a];
+      o->om[k][a] = omega[3 * k + a];
+      o->ctr[k][a] = center[3 * k + a];
+      o->box_lo[k][a] = k > 0 ? lo[3 * k + a] : 0.0;
+      o->box_hi[k][a] = k > 0 ? hi[3 * k + a] : 0.0;
+    }
   return 0;
 }
 
@@ -1372,8 +1423,13 @@ ORC_API double orc_compute_dt(void* h, double cfl) { return static_cast<Oracle*>
 ORC_API int orc_step(void* h, double dt) {
   Oracle* o = static_cast<Oracle*>(h);
   o->step(dt);
-  // the rigid centre moves with the translational velocity
-  for (int a = 0; a < 3; ++a) o->ctr[a] += o->vr[a] * dt;
+  // each body's centre and ownership box move with its translational velocity
+  for (int k = 0; k < o->nbody; ++k)
+    for (int a = 0; a < 3; ++a) {
+      o->ctr[k][a] += o->vr[k][a] * dt;
+      o->box_lo[k][a] += o->vr[k][a] * dt;
+      o->box_hi[k][a] += o->vr[k][a] * dt;
+    }
   return 0;
 }
 
