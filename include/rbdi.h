@@ -123,9 +123,16 @@ typedef struct {
   long long band_cells;   /* rigid cells with a nonzero normal (last band build) */
   long long seeded;       /* cells seeded (cumulative over steps) */
   long long probe_fail;   /* of band_cells, those without a valid probe (last band build) */
-  int nonphysical;        /* 1 once a non-admissible updated cell was found */
+  int nonphysical;        /* 1 once a non-admissible updated cell was found: after
+                             every stage, a non-positive phasic mass or a
+                             non-finite energy; at the end of every step, in
+                             non-rigid cells, also a volume fraction outside
+                             [0,1], a non-positive mixture sound speed
+                             squared or a non-finite signal speed */
   long long first_bad;    /* linear interior index of the first such cell, or -1 */
-  long long surr_net;     /* plastic-return evaluations closed by the surrogate (cumulative) */
+  long long surr_net;     /* plastic-return evaluations closed by the surrogate (cumulative;
+                             cells that provably cannot yield skip the closure
+                             and are not counted) */
   long long surr_exact;   /* ... closed by the exact closure: outside the envelope or flagged */
 } rbdi_stats;
 
@@ -174,9 +181,28 @@ RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device)
 RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device, double width,
                                 const double v[3], const double omega[3], const double center[3]);
 
-/* Replace the rigid motion (velocity, angular velocity, centre). */
+/* Replace the rigid motion (velocity, angular velocity, centre) by that of
+ * a single body (every point moves with it). */
 RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3],
                                    const double center[3]);
+
+/* Several rigid bodies with their own motions in one instance (the paper's
+ * extrusion test, Sec. 4.5: a moving piston and a static wedge in one r
+ * field). r is set as before from the union's signed distance
+ * (rbdi_set_rigid_sdf); this call replaces the motion by a table of nbody
+ * (1..RBDI_MAX_BODIES) motions: v, omega, center (host, nbody x 3 each)
+ * and, for bodies 1..nbody-1, an ownership box box_lo <= x < box_hi (host,
+ * nbody x 3; row 0 ignored, may be NULL when nbody = 1). A point moves with
+ * the first body k >= 1 whose box holds it, otherwise with body 0: the
+ * rigid velocity v_k + omega_k x (x - c_k) (Sec. 2.3) of that body enters
+ * the r flux, the seeding states and the CFL rate. Centres and boxes are
+ * those of the current time and move with each body's velocity. A box must
+ * hold its body's whole diffuse r profile (r below rounding at the box
+ * faces). BAD_ARG for nbody out of range, non-finite motions or NaN box
+ * bounds (infinite bounds are allowed). */
+#define RBDI_MAX_BODIES 4
+RBDI_API int rbdi_set_rigid_bodies(rbdi_handle* h, int nbody, const double* v, const double* omega,
+                                   const double* center, const double* box_lo, const double* box_hi);
 
 /* CFL time step: dt = cfl * min over non-rigid cells and directions of
  * dx_d / max(|u_d| + c, |v_r,d|) (Sec. 3: a fraction of the global maximum
@@ -219,7 +245,8 @@ RBDI_API int rbdi_conserved_totals(rbdi_handle* h, double* out);
  * elapsed times per class into ms[class] (milliseconds) and launches[class],
  * and releases the recorded pairs. Classes: 0 sweep along x (the last sweep,
  * with the RK combine), 1 sweep along y, 2 sweep along z, 3 seeding, 4 rigid
- * band compaction, 5 CFL reduction, 6 surrogate source pass. ms and launches
+ * band compaction, 5 CFL reduction, 6 unused (the surrogate sources run
+ * inside the x sweep, class 0). ms and launches
  * hold RBDI_NUM_KCLASS entries each. */
 #define RBDI_NUM_KCLASS 7
 RBDI_API int rbdi_set_kernel_timing(rbdi_handle* h, int enable);
@@ -347,10 +374,13 @@ RBDI_API int rbdi_batch_advance(rbdi_batch* b, double cfl, int nsteps, double t_
  * of Sec. 2.1.2) beyond their series to order X^3, from six invariant
  * features of X. With a network set on a solid handle (rbdi_set_surrogate)
  * the per-stage elastoplastic sources (det(Vbar) renormalisation and the
- * perfect-plasticity radial return) run in a separate pass that takes H and
- * J2 = H:H from the network; outside the envelope |X|_F <= tau_max, or when
- * the network's J2 disagrees with the one its H implies by more than 1e-6
- * relative (the error flag), that cell uses the exact closure.
+ * perfect-plasticity radial return) take H and J2 = H:H from the network,
+ * evaluated inside the final (x) sweep of each stage, one matrix tile per
+ * wavefront of 64 cells; outside the envelope |X|_F <= tau_max, or when the
+ * error flag is raised (the network's J2 disagrees with the one its H
+ * implies by more than 1e-6 relative, or its H violates tr H = 0, the
+ * identity of a unit-determinant stretch, by more than 1e-6 |H|), that cell
+ * uses the exact closure.
  * Parameter vector: FP32, 9158 values, row-major [out][in] per layer:
  * W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[6][64] b4[6].
  * Features z and targets t: n x 6 FP32, sample-major. All calls below run

@@ -20,6 +20,13 @@ HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep packed-FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Kernels take the launch parameters (a ~2 KB struct) by value and read
+    # them through references. Clang copies such an argument into a private
+    # stack slot, which InstCombine folds back into reads of the kernel
+    # argument only while the slot has at most 300 users (its default); the
+    # sweeps with the most inlined physics exceed that, and the copy then
+    # lands in scratch memory (2 KB per lane).
+    "-mllvm", "-instcombine-max-copied-from-constant-users=4000",
 ]
 
 

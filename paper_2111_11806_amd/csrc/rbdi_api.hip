@@ -185,9 +185,16 @@ struct Impl {
     launch(h, 4, k_band<S, T>, dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->P, (const T*)u(h, 0), h->tasks,
            h->task_cap, h->sc, A);
   }
+  // Launches with more than one rigid body take the kernels that test the
+  // ownership boxes (rigid_velocity<true>); the others leave that code out.
+  static bool multi(const rbdi_handle* h) { return h->P.nbody > 1; }
   static void seed(rbdi_handle* h, const StepArgs& A) {
-    launch(h, 3, k_seed<S, T>, dim3(256), dim3(256), 0, h->P, u(h, 0), (const SeedTask*)h->tasks, h->task_cap,
-           h->sc, A);
+    if (multi(h))
+      launch(h, 3, k_seed<S, T, true>, dim3(256), dim3(256), 0, h->P, u(h, 0), (const SeedTask*)h->tasks,
+             h->task_cap, h->sc, A);
+    else
+      launch(h, 3, k_seed<S, T, false>, dim3(256), dim3(256), 0, h->P, u(h, 0), (const SeedTask*)h->tasks,
+             h->task_cap, h->sc, A);
   }
   // Wavefronts per x-sweep block: 1 in 1D; in 2D, 4 or 2, whichever leaves
   // fewer idle wavefronts at the end of a row (4 on ties; measured on the
@@ -207,9 +214,21 @@ struct Impl {
     const unsigned w = (unsigned)x_wpb(h);
     return dim3((nseg + w - 1) / w, (unsigned)P.n[1], (unsigned)P.n[2]);
   }
-  static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
-    launch(h, 0, k_sweep_x<S, T>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
+  template <bool MB>
+  static void sweep_x_mb(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
+    if constexpr (S::S) {
+      if (h->P.surr) {  // the surrogate sources inside the final sweep
+        launch(h, 0, k_sweep_x_surr<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0,
+               (const T*)h->D, Uout, h->sc, h->cflpart, A, b, stage, mlp_dev(h->mlp));
+        return;
+      }
+    }
+    launch(h, 0, k_sweep_x<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
            h->sc, h->cflpart, A, b, stage);
+  }
+  static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
+    if (multi(h)) sweep_x_mb<true>(h, Uin, U0, Uout, A, b, stage);
+    else sweep_x_mb<false>(h, Uin, U0, Uout, A, b, stage);
   }
   template <int DIR, int MODE, bool REDUCE>
   static void sweep_t(rbdi_handle* h, const T* Uin, const StepArgs& A) {
@@ -218,20 +237,16 @@ struct Impl {
     const unsigned nseg = (unsigned)((P.n[DIR] + kOut - 1) / kOut);
     const unsigned gx = (unsigned)((P.n[0] + TC - 1) / TC);
     const dim3 grid = DIR == 1 ? dim3(gx, nseg, (unsigned)P.n[2]) : dim3(gx, (unsigned)P.n[1], nseg);
-    launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE>, grid, dim3(kTileThreads), 0, P, Uin, static_cast<T*>(h->D), h->sc,
-           (const double*)h->cflpart, A);
-  }
-  static void sources_mlp(rbdi_handle* h, T* Uout, const StepArgs& A, int stage) {
-    if constexpr (S::S)
-      launch(h, 6, k_sources_mlp<S, T>, dim3(blocks_for(h->P.ncell, 256)), dim3(256), 0, h->P, Uout,
-             (const T*)u(h, 0), mlp_dev(h->mlp), h->sc, h->cflpart, A, stage);
+    if (multi(h))
+      launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE, true>, grid, dim3(kTileThreads), 0, P, Uin,
+             static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
+    else
+      launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE, false>, grid, dim3(kTileThreads), 0, P, Uin,
+             static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
   }
   static void stages(rbdi_handle* h, const StepArgs& A) {
     const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
-    // with the surrogate pass the last stage writes U(1)'s buffer (U^n stays
-    // intact for the pass's rigid mask) and the buffers swap afterwards
-    const bool surr = h->P.surr != 0;
-    const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, surr ? 1 : 0};
+    const int in_[3] = {0, 1, 2}, out_[3] = {1, 2, 0};
     if constexpr (S::D == 1) launch(h, 5, k_reduce_dt, dim3(1), dim3(256), 0, h->sc, (const double*)h->cflpart, A);
     for (int s = 0; s < 3; ++s) {
       const T* Uin = u(h, in_[s]);
@@ -246,13 +261,15 @@ struct Impl {
         else sweep_t<1, 0, false>(h, Uin, A);
       }
       sweep_x(h, Uin, U0, Uout, A, bc[s], s);
-      if (surr) sources_mlp(h, Uout, A, s);
     }
-    if (surr) std::swap(h->U[0], h->U[1]);
   }
   static void cfl(rbdi_handle* h) {
-    launch(h, 5, k_cfl<S, T>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->P, (const T*)u(h, 0), h->sc, h->par,
-           h->cflpart);
+    if (multi(h))
+      launch(h, 5, k_cfl<S, T, true>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->P, (const T*)u(h, 0), h->sc,
+             h->par, h->cflpart);
+    else
+      launch(h, 5, k_cfl<S, T, false>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->P, (const T*)u(h, 0), h->sc,
+             h->par, h->cflpart);
   }
   static void force(rbdi_handle* h, const double* c) {
     hipLaunchKernelGGL((k_force_partial<S, T>), dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream, h->P,
@@ -468,6 +485,7 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   DevScalars zero{};
   zero.first_bad = -1;
   P.r_static = 1;
+  P.nbody = 1;  // one body at rest until a motion is set
   e = hipMemcpy(h->sc, &zero, sizeof(zero), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->U[0], 0, state_bytes);
   if (e != hipSuccess) {
@@ -640,23 +658,42 @@ RBDI_API int rbdi_set_rigid_sdf(rbdi_handle* h, const double* sdf, int on_device
 
 __global__ void k_set_motion_time(DevScalars* sc, int par) { sc->t_motion = sc->t[par]; }
 
-RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3], const double center[3]) {
-  if (!h || !v || !omega || !center) return fail(RBDI_ERR_BAD_ARG, "null argument");
+static_assert(RBDI_MAX_BODIES == kMaxBody, "the body table of the header and of the kernels differ");
+
+RBDI_API int rbdi_set_rigid_bodies(rbdi_handle* h, int nbody, const double* v, const double* omega,
+                                   const double* center, const double* box_lo, const double* box_hi) {
+  if (!h || !v || !omega || !center || (nbody > 1 && (!box_lo || !box_hi)))
+    return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (nbody < 1 || nbody > kMaxBody) return fail(RBDI_ERR_BAD_ARG, "nbody must be 1.." + std::to_string(kMaxBody));
   if (free_member(h)) return RBDI_ERR_NOT_READY;
+  for (int k = 0; k < nbody; ++k)
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(v[3 * k + a]) || !std::isfinite(omega[3 * k + a]) || !std::isfinite(center[3 * k + a]))
+        return fail(RBDI_ERR_BAD_ARG, "non-finite rigid motion");
+      if (k > 0 && (std::isnan(box_lo[3 * k + a]) || std::isnan(box_hi[3 * k + a])))
+        return fail(RBDI_ERR_BAD_ARG, "NaN ownership box");
+    }
   bool moving = false;
-  for (int a = 0; a < 3; ++a) {
-    if (!std::isfinite(v[a]) || !std::isfinite(omega[a]) || !std::isfinite(center[a]))
-      return fail(RBDI_ERR_BAD_ARG, "non-finite rigid motion");
-    h->P.vr[a] = v[a];
-    h->P.om[a] = omega[a];
-    h->P.ctr[a] = center[a];
-    moving = moving || v[a] != 0.0 || omega[a] != 0.0;
-  }
+  h->P.nbody = nbody;
+  for (int k = 0; k < kMaxBody; ++k)
+    for (int a = 0; a < 3; ++a) {
+      const bool on = k < nbody;
+      h->P.vr[k][a] = on ? v[3 * k + a] : 0.0;
+      h->P.om[k][a] = on ? omega[3 * k + a] : 0.0;
+      h->P.ctr[k][a] = on ? center[3 * k + a] : 0.0;
+      h->P.blo[k][a] = (on && k > 0) ? box_lo[3 * k + a] : -HUGE_VAL;
+      h->P.bhi[k][a] = (on && k > 0) ? box_hi[3 * k + a] : HUGE_VAL;
+      moving = moving || (on && (v[3 * k + a] != 0.0 || omega[3 * k + a] != 0.0));
+    }
   h->dynamic_r = moving;
   h->P.r_static = moving ? 0 : 1;
   h->cfl_valid = false;
   hipLaunchKernelGGL(k_set_motion_time, dim3(1), dim3(1), 0, h->stream, h->sc, h->par);
   return check_launch();
+}
+
+RBDI_API int rbdi_set_rigid_motion(rbdi_handle* h, const double v[3], const double omega[3], const double center[3]) {
+  return rbdi_set_rigid_bodies(h, 1, v, omega, center, nullptr, nullptr);
 }
 
 // One step: (CFL minimum if stale) -> band (once for a static body) ->
@@ -816,8 +853,8 @@ RBDI_API int rbdi_autotune(rbdi_handle* h, double cfl, int nsteps, int* best, do
   if (free_member(h)) return RBDI_ERR_NOT_READY;
   if (!h->have_state) return fail(RBDI_ERR_NOT_READY, "no state set");
   // everything a step changes that a later step reads: the state (U^n and
-  // the buffer order, which the surrogate pass swaps), the device scalars,
-  // the CFL partials, and the host-side step bookkeeping
+  // the buffer order), the device scalars, the CFL partials, and the
+  // host-side step bookkeeping
   const size_t state_bytes = (size_t)h->P.fs * h->nf * h->elem;
   const size_t part_bytes = sizeof(double) * (size_t)h->part_cap;
   char* save = nullptr;

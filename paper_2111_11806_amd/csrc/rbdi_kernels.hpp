@@ -216,23 +216,32 @@ __device__ inline double r_at(const Params& P, const T* __restrict__ U, int i, i
 // ---------------------------------------------------------------------------
 
 // CFL signal rate of one cell: max_d max(|u_d| + c, |v_r,d|) / dx_d
-// (dt = cfl / max over fluid cells; mixture sound speed of Sec. 2.2).
-template <class S, typename T>
-__device__ inline double cfl_rate(const Params& P, const T* Uc, const double* x, double tc) {
+// (dt = cfl / max over fluid cells; mixture sound speed of Sec. 2.2). With
+// adm, also whether the cell's state is admissible: positive phasic
+// densities, volume fractions in [0,1], a positive mixture sound speed
+// squared (a phase present only in trace may sit outside its own
+// admissible range, as trace air inside water under tension), a finite rate.
+template <class S, typename T, bool MB = false>
+__device__ inline double cfl_rate(const Params& P, const T* Uc, const double* x, double tc, bool* adm = nullptr) {
   T W[S::NF];
   double J2 = 0.0;
   cons_to_prim<S>(P, Uc, W, nullptr, &J2);
   double phi[kMaxMat], rl[kMaxMat], c2, G, sY;
   phases_w<S>(W, phi, rl);
   mix_c2_G<S>(P, phi, rl, J2, (double)W[S::wP], c2, G, sY);
-  const double cs = sqrt(c2);
-  double xs[3], v[3];
+  if (adm) {
+    bool ok = c2 > 0.0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) xs[a] = x[a] - P.vr[a] * tc;
-  rigid_velocity(P, xs, v);
+    for (int l = 0; l < S::N; ++l) ok = ok && rl[l] > 0.0 && phi[l] >= 0.0 && phi[l] <= 1.0;
+    *adm = ok;
+  }
+  const double cs = sqrt(c2);
+  double v[3];
+  rigid_velocity<MB>(P, x, tc, v);
   double m = 0.0;
 #pragma unroll
   for (int d = 0; d < S::D; ++d) m = fmax(m, fmax(fabs((double)W[S::wU(d)]) + cs, fabs(v[d])) * P.inv_dx[d]);
+  if (adm) *adm = *adm && isfinite(m);
   return m;
 }
 
@@ -243,7 +252,7 @@ __device__ inline double cfl_rate(const Params& P, const T* Uc, const double* x,
 // the right of each cell, the upwind r flux, and this direction's part of
 // D = (F_+ - F_-)/dx - s_non-con (Sec. 3.1) for the cell. All lanes execute
 // it (cross-lane shuffles); only lanes 3..60 get a complete d.
-template <class S, typename T, int DIR>
+template <class S, typename T, int DIR, bool MB = false>
 __device__ inline void sweep_core(const Params& P, const T* W, int pos, const int* pc, double tc, T* d) {
   constexpr bool Z = !S::S;  // zero-filling shifts (see dpp_shr1)
   T sL[S::NF], sR[S::NF];
@@ -278,10 +287,10 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
   if (!P.r_static) {
     double xf[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xf[a] = (a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0) - P.vr[a] * tc;
-    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR] - P.vr[DIR] * tc;
+    for (int a = 0; a < 3; ++a) xf[a] = a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0;
+    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR];
     double v[3];
-    rigid_velocity(P, xf, v);
+    rigid_velocity<MB>(P, xf, tc, v);
     vf = (T)v[DIR];
     rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
   }
@@ -323,7 +332,7 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
 // 3..60 carry a complete d). The flux and update arrays of sweep_core are
 // never held in registers, which keeps these 18-field sweeps within two
 // wavefronts' register budget per SIMD.
-template <class S, typename T, int DIR, class Put>
+template <class S, typename T, int DIR, bool MB, class Put>
 __device__ inline void sweep_core_streamed(const Params& P, const T* W, int pos, const int* pc, double tc, Put&& put) {
   constexpr bool Z = false;
   T sL[S::NF], sR[S::NF];
@@ -361,10 +370,10 @@ __device__ inline void sweep_core_streamed(const Params& P, const T* W, int pos,
   if (!P.r_static) {
     double xf[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xf[a] = (a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0) - P.vr[a] * tc;
-    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR] - P.vr[DIR] * tc;
+    for (int a = 0; a < 3; ++a) xf[a] = a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0;
+    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR];
     double v[3];
-    rigid_velocity(P, xf, v);
+    rigid_velocity<MB>(P, xf, tc, v);
     vf = (T)v[DIR];
     rfl = vf > T(0) ? sR[S::R] * vf : (vf < T(0) ? WR[S::R] * vf : T(0));
   }
@@ -422,12 +431,35 @@ __device__ inline void ghost_fix(const Params& P, int mode, int face, T* W) {
 template <class S>
 constexpr int sweep_max_threads() { return 256; }
 
-template <class S, typename T>
+// No-op per-cell sources (systems without a stretch tensor).
+struct NoSources {
+  template <class S, typename T>
+  __device__ void operator()(const Params&, T*, bool) const {}
+};
+
+// The exact elastoplastic sources of one cell (det(Vbar) renormalisation and
+// the plastic return), applied by each lane to its own updated cell.
+struct ExactSources {
+  template <class S, typename T>
+  __device__ void operator()(const Params& P, T* Un, bool act) const {
+    if constexpr (S::S) {
+      if (act) solid_sources<S>(P, Un);
+    }
+  }
+};
+
+// The final x sweep of a stage. xw: this wavefront's LDS slots of the
+// streamed d (elastoplastic systems; NF x 64 values). src(P, Un, act) applies
+// the per-cell sources to the updated state Un; every lane of the wavefront
+// calls it (act: the lane holds an updated non-rigid cell), so a source step
+// may work across the wavefront (the surrogate's matrix instructions).
+template <class S, typename T, class Src = ExactSources, bool MB = false>
 __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restrict__ Uin, const T* __restrict__ U0,
                                              const T* __restrict__ Dacc, T* __restrict__ Uout,
                                              DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                              const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
-                                             long long blin, int wpb, int nparts, T* xlds = nullptr) {
+                                             long long blin, int wpb, int nparts, T* xw = nullptr,
+                                             const Src& src = Src()) {
   const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
   const int lane = threadIdx.x & (kWave - 1);
@@ -436,9 +468,9 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   // cache lines shared by neighbouring segments are fetched once
   const int seg = bx * wpb + wave, j = by, k = bz;
   const size_t part_slot = (size_t)blin * wpb + wave;
-  if (stage == 2 && blin == 0 && threadIdx.x == 0 && !P.surr) sc->npart = nparts;
+  if (stage == 2 && blin == 0 && threadIdx.x == 0) sc->npart = nparts;
   if (seg * kOut >= P.n[0]) {  // whole wavefront beyond the row
-    if (stage == 2 && lane == 0 && !P.surr) cflpart[part_slot] = 0.0;
+    if (stage == 2 && lane == 0) cflpart[part_slot] = 0.0;
     return;
   }
   const int nd = P.n[0];
@@ -460,40 +492,42 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   if constexpr (S::S) {
     // streamed: this lane's d goes through its own LDS slots (no other lane
     // reads them); U_in is reloaded for the combine instead of being held
-    T* my = xlds + (size_t)wave * S::NF * kWave + lane;
-    sweep_core_streamed<S, T, 0>(P, W, pos, pc, tc, [&](int q, T v) { my[q * kWave] = v; });
+    T* my = xw + lane;
+    sweep_core_streamed<S, T, 0, MB>(P, W, pos, pc, tc, [&](int q, T v) { my[q * kWave] = v; });
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) d[q] = my[q * kWave];
   } else {
-    sweep_core<S, T, 0>(P, W, pos, pc, tc, d);
+    sweep_core<S, T, 0, MB>(P, W, pos, pc, tc, d);
   }
   if (A.rhs_only & 2) {
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) d[q] = T(0);
   }
   const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
-  double rate = 0.0;
-  if (outlane) {
-    const long long c = cell_index(P, pos, j, k);
-    if (S::D > 1) {
-      // with a static body r's operator is zero and the y/z sweeps do not
-      // store its row of D: the loaded value is discarded by a select (a
-      // branch around the loads measured slower than the bytes it saves)
+  const long long c = outlane ? cell_index(P, pos, j, k) : 0;
+  if (outlane && S::D > 1) {
+    // with a static body r's operator is zero and the y/z sweeps do not
+    // store its row of D: the loaded value is discarded by a select (a
+    // branch around the loads measured slower than the bytes it saves)
 #pragma unroll
-      for (int q = 0; q < S::NF; ++q) {
-        const T dq = Dacc[q * P.fs + c];
-        d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
-      }
+    for (int q = 0; q < S::NF; ++q) {
+      const T dq = Dacc[q * P.fs + c];
+      d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
     }
-    if (A.rhs_only) {
+  }
+  if (A.rhs_only) {  // uniform over the grid
+    if (outlane) {
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = d[q];
-      return;
     }
+    return;
+  }
+  T Un[S::NF];
+  bool rigid = false;
+  if (outlane) {
     const T dtt = (T)dt;
     const T b = (T)bcoef;
-    const bool rigid = (double)U0[S::R * P.fs + c] > 0.5;
-    T Un[S::NF];
+    rigid = (double)U0[S::R * P.fs + c] > 0.5;
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) {
       // an output lane is an interior cell: U_in is its own load
@@ -506,9 +540,10 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
         Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
       }
     }
-    if constexpr (S::S) {
-      if (!rigid && !P.surr) solid_sources<S>(P, Un);
-    }
+  }
+  src.template operator()<S, T>(P, Un, outlane && !rigid);
+  double rate = 0.0;
+  if (outlane) {
     bool ok = true;
 #pragma unroll
     for (int l = 0; l < S::N; ++l) ok = ok && (Un[S::cA(l)] > T(0));
@@ -518,15 +553,19 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     }
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) Uout[q * P.fs + c] = Un[q];
-    if (stage == 2 && !P.surr && !((double)Un[S::R] > 0.5)) {
+    if (stage == 2 && !((double)Un[S::R] > 0.5)) {
       double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pc[a] + 0.5) * P.dx[a];
       x[0] = P.x0[0] + (pos + 0.5) * P.dx[0];
-      rate = cfl_rate<S>(P, Un, x, tc + dt);
+      bool adm;
+      rate = cfl_rate<S, T, MB>(P, Un, x, tc + dt, &adm);
+      // the full admissibility test of the step's result (the closure is
+      // at hand here); the earlier stages test positivity and finiteness
+      if (!adm && atomicExch(&sc->nonphys, 1) == 0) sc->first_bad = c;
     }
   }
-  if (stage == 2 && !P.surr) {
+  if (stage == 2) {
     for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
     if (lane == 0) cflpart[part_slot] = rate;
   }
@@ -543,7 +582,7 @@ constexpr int x_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 4; }
 template <class S>
 constexpr int tile_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 3; }
 
-template <class S, typename T>
+template <class S, typename T, bool MB = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
                                                 const T* __restrict__ Dacc, T* __restrict__ Uout,
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
@@ -553,11 +592,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
   const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
   if constexpr (S::S) {
     __shared__ T xlds[kMaxWPB * S::NF * kWave];
-    sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
-                       blin, wpb, nparts, xlds);
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x,
+                                         blockIdx.y, blockIdx.z, blin, wpb, nparts,
+                                         xlds + (threadIdx.x / kWave) * S::NF * kWave);
   } else {
-    sweep_x_body<S, T>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x, blockIdx.y, blockIdx.z,
-                       blin, wpb, nparts);
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x,
+                                         blockIdx.y, blockIdx.z, blin, wpb, nparts);
   }
 }
 
@@ -579,7 +619,7 @@ constexpr int tile_cols() {
        : (S::NF * 8 * kRS * (int)sizeof(T) <= 48 * 1024) ? 8 : 4;
 }
 
-template <class S, typename T, int DIR, int MODE, bool REDUCE>
+template <class S, typename T, int DIR, int MODE, bool REDUCE, bool MB = false>
 __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                 DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                 const StepArgs& A, int bx, int by, int bz, T* tile,
@@ -660,12 +700,12 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
       // tile column (its U_in there was consumed by the closure above; the
       // slots of halo lanes and of positions beyond the domain are written
       // too, and never read: the store below takes the output rows only)
-      sweep_core_streamed<S, T, DIR>(P, W, pos, pc, tc, [&](int q, T v) {
+      sweep_core_streamed<S, T, DIR, MB>(P, W, pos, pc, tc, [&](int q, T v) {
         tile[(q * TC + c) * kRS + lane] = zero ? T(0) : v;
       });
     } else {
       T d[S::NF];
-      sweep_core<S, T, DIR>(P, W, pos, pc, tc, d);
+      sweep_core<S, T, DIR, MB>(P, W, pos, pc, tc, d);
       if (zero) {
 #pragma unroll
         for (int q = 0; q < S::NF; ++q) d[q] = T(0);
@@ -695,14 +735,14 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
   }
 }
 
-template <class S, typename T, int DIR, int MODE, bool REDUCE>
+template <class S, typename T, int DIR, int MODE, bool REDUCE, bool MB = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(tile_sweep_waves<S>()))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                    DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                    StepArgs A) {
   constexpr int TC = tile_cols<S, T>();
   __shared__ T tile[S::NF * TC * kRS];
-  sweep_tile_body<S, T, DIR, MODE, REDUCE>(P, Uin, Dacc, sc, cflpart, A, blockIdx.x, blockIdx.y, blockIdx.z, tile,
-                                           TC);
+  sweep_tile_body<S, T, DIR, MODE, REDUCE, MB>(P, Uin, Dacc, sc, cflpart, A, blockIdx.x, blockIdx.y, blockIdx.z,
+                                               tile, TC);
 }
 
 // ---------------------------------------------------------------------------
@@ -846,8 +886,11 @@ __device__ inline bool band_normal(const Params& P, const T* __restrict__ U, int
 // Seeding geometry of one rigid cell (Sec. 3.2 steps 1-2): outward normal,
 // probe along n at 1, 1.5, ..., 4 dx (or the fixed 1.5 dx); the first point
 // whose enclosing cells with a nonzero interpolation weight are all interior
-// with r <= 0.5 is used. It depends on r only, so for a static body it is
-// computed once and reused by every step.
+// with r <= 0.5 is used. A point between the outermost cell centres and a
+// domain face is moved, along that axis, onto the outermost centre, so that
+// a probe running along a wall does not switch between valid and invalid
+// with the sign of a rounding error. It depends on r only, so for a static
+// body it is computed once and reused by every step.
 struct SeedTask {
   int c;          // linear index of the rigid cell
   int lo[3];      // lower corner of the interpolation support
@@ -902,7 +945,10 @@ __global__ __launch_bounds__(256) void k_band(Params P, const T* __restrict__ U,
       double w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < S::D; ++a) {
-        const double xi = pi[a] + dist * n[a] * (P.dmin * P.inv_dx[a]);
+        double xi = pi[a] + dist * n[a] * (P.dmin / P.dx[a]);
+        const double last = (double)(P.n[a] - 1);
+        xi = (xi < 0.0 && xi >= -0.5) ? 0.0 : xi;
+        xi = (xi > last && xi <= last + 0.5) ? last : xi;
         lo[a] = (int)floor(xi);
         w[a] = xi - lo[a];
       }
@@ -937,7 +983,7 @@ __global__ void k_band_reset(DevScalars* sc, StepArgs A) {
 // optional Riemann star state, written to the thermodynamic fields of the
 // rigid cell. Support cells are never rigid, so no thread reads a cell that
 // another one writes.
-template <class S, typename T>
+template <class S, typename T, bool MB = false>
 __device__ __forceinline__ void seed_one(const Params& P, T* __restrict__ U, const SeedTask& t, double tc) {
   double Wc[1 << S::D][S::NF];
 #pragma unroll
@@ -969,10 +1015,8 @@ __device__ __forceinline__ void seed_one(const Params& P, T* __restrict__ U, con
   double xc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < S::D; ++a) xc[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) xc[a] -= P.vr[a] * tc;
   double v[3];
-  rigid_velocity(P, xc, v);
+  rigid_velocity<MB>(P, xc, tc, v);
   double Wm[S::NF], Wg[S::NF];
   mirror<S>(Wc[0], t.n, v, Wm);
   if (P.seed == SEED_RIEMANN) riemann_seed<S>(P, Wm, Wc[0], t.n, Wg);
@@ -996,7 +1040,7 @@ __device__ inline void wave_count_add(long long* counter, int v) {
   if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long*)counter, (unsigned long long)v);
 }
 
-template <class S, typename T>
+template <class S, typename T, bool MB = false>
 __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const SeedTask* __restrict__ tasks,
                                              int cap, DevScalars* __restrict__ sc, StepArgs A) {
   if (step_done(sc, A)) return;
@@ -1004,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_seed(Params P, T* __restrict__ U, const
   const double tc = sc->t[A.par] - sc->t_motion;
   int nseed = 0;
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-    seed_one<S, T>(P, U, tasks[b], tc);
+    seed_one<S, T, MB>(P, U, tasks[b], tc);
     ++nseed;
   }
   wave_count_add(&sc->seeded, nseed);
@@ -1047,7 +1091,7 @@ __device__ inline double block_sum(double v, double* sh) {
 
 // CFL partials (one per block) of the current state, for a state that did
 // not come from a step; the first sweep of the next step reduces them.
-template <class S, typename T>
+template <class S, typename T, bool MB = false>
 __global__ __launch_bounds__(kRedThreads) void k_cfl(Params P, const T* __restrict__ U,
                                                     DevScalars* __restrict__ sc, int par,
                                                     double* __restrict__ part) {
@@ -1064,7 +1108,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cfl(Params P, const T* __restri
     double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
-    m = fmax(m, cfl_rate<S>(P, Uc, x, tc));
+    m = fmax(m, cfl_rate<S, T, MB>(P, Uc, x, tc));
   }
   m = -block_min(-m, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = m;

@@ -527,129 +527,135 @@ __global__ void k_mlp_data(const double* __restrict__ V, int n, double tau_max, 
 }
 
 // ---------------------------------------------------------------------------
-// Elastoplastic sources with the surrogate (one pass after the final sweep
-// of each stage): det(Vbar) renormalisation, H and J2 = H:H from the network
-// inside the envelope (exact closure outside it, or when the network's J2
-// disagrees with the one its own H implies: the error flag), perfect-
+// Elastoplastic sources with the surrogate, inside the final sweep of each
+// stage (SurrogateSources, called by every lane of the wavefront on its
+// updated cell): det(Vbar) renormalisation; H and J2 = H:H from the network
+// (the wavefront's 64 cells are one matrix tile) inside the envelope, the
+// exact closure outside it or where the error flag is raised; perfect-
 // plasticity radial return Vbar <- exp((s-1) H) Vbar with
-// eps_p += sqrt(2/3)(1-s)|H|; in the last stage also the CFL partials.
+// eps_p += sqrt(2/3)(1-s)|H|. Error flag: the network's J2 (from its H^2
+// coefficients) disagrees with the J2 of its own H by more than 1e-6
+// relative, or its H violates the identity tr H = (1/2) ln det(Vbar Vbar^T)
+// = 0 of the renormalised stretch by more than 1e-6 |H|.
 // ---------------------------------------------------------------------------
+struct SurrogateSources {
+  MlpDev m;
+  MlpWaveLds* L;        // this wavefront's LDS tile
+  DevScalars* sc;       // counters of network / exact closures
 
-template <class S, typename T>
-__global__ __launch_bounds__(256) void k_sources_mlp(Params P, T* __restrict__ U, const T* __restrict__ U0, MlpDev m,
-                                                    DevScalars* __restrict__ sc, double* __restrict__ cflpart,
-                                                    StepArgs A, int stage) {
-  __shared__ MlpWaveLds lds[4];
-  if (sc->dtv[A.par] == 0.0) return;  // uniform over the grid
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = c < P.ncell;
-  const bool act = in && !((double)U0[S::R * P.fs + c] > 0.5);
-  T Uc[S::NF];
-  double V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  if (act) {
-    load_cons<S>(P, U, c, Uc);
+  template <class S, typename T>
+  __device__ void operator()(const Params& P, T* Un, bool act) const {
+    if constexpr (S::S) {
+      // the tile shares its LDS with the sweep's d, which every lane has read
+      wave_sync_lds();
+      double V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      if (act) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) V[q] = (double)Uc[S::cV(0, 0) + q];
-    const double det = V[0] * (V[4] * V[8] - V[5] * V[7]) - V[1] * (V[3] * V[8] - V[5] * V[6]) +
-                       V[2] * (V[3] * V[7] - V[4] * V[6]);
-    const double scl = 1.0 / cbrt(det);
+        for (int q = 0; q < 9; ++q) V[q] = (double)Un[S::cV(0, 0) + q];
+        const double det = V[0] * (V[4] * V[8] - V[5] * V[7]) - V[1] * (V[3] * V[8] - V[5] * V[6]) +
+                           V[2] * (V[3] * V[7] - V[4] * V[6]);
+        const double scl = 1.0 / cbrt(det);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) V[q] *= scl;
-  }
-  const StrainInv si = strain_invariants(V);
-  const bool env = act && P.plastic && si.tau <= m.tau_max;
-  float z[6] = {0, 0, 0, 0, 0, 0}, y[6];
-  if (env) mlp_features(si, m.tau_max, z);
-  mlp_wave_forward(m, &lds[wave], z, y);
-  int used_net = 0, used_exact = 0;
-  if (act && P.plastic) {
-    double H[9], J2 = 0.0;
-    bool ok = env;
-    if (ok) {
-      double a[3], cc[3];
-      mlp_decode(si, y, a, cc);
-      const SymM& X = si.X;
-      const SymM& X2 = si.X2;
-      const double h00 = a[0] + a[1] * X.a00 + a[2] * X2.a00, h11 = a[0] + a[1] * X.a11 + a[2] * X2.a11;
-      const double h22 = a[0] + a[1] * X.a22 + a[2] * X2.a22, h01 = a[1] * X.a01 + a[2] * X2.a01;
-      const double h02 = a[1] * X.a02 + a[2] * X2.a02, h12 = a[1] * X.a12 + a[2] * X2.a12;
-      H[0] = h00; H[1] = h01; H[2] = h02; H[3] = h01; H[4] = h11; H[5] = h12; H[6] = h02; H[7] = h12; H[8] = h22;
-      const double j2h = h00 * h00 + h11 * h11 + h22 * h22 + 2.0 * (h01 * h01 + h02 * h02 + h12 * h12);
-      // J2 = tr(H^2) from the network's H^2 coefficients (tr X^2 = tau^2)
-      J2 = 3.0 * cc[0] + cc[1] * si.e1 + cc[2] * si.tau * si.tau;
-      ok = fabs(J2 - j2h) <= 1e-6 * j2h + 1e-300;  // error flag
-      J2 = j2h;
-    }
-    if (!ok) hencky3(V, H, J2);
-    used_net = ok ? 1 : 0;
-    used_exact = ok ? 0 : 1;
-    // closure terms of the plastic return: phases, pressure, G, yield
-    T Ut[S::NF];
-#pragma unroll
-    for (int q = 0; q < S::NF; ++q) Ut[q] = Uc[q];
-    double rho = 0.0;
-#pragma unroll
-    for (int l = 0; l < S::N; ++l) rho += (double)Ut[S::cA(l)];
-    double phi[kMaxMat], rl[kMaxMat], sph = 0.0;
-#pragma unroll
-    for (int l = 0; l < S::N - 1; ++l) {
-      phi[l] = (double)Ut[S::cPHI(l)];
-      sph += phi[l];
-    }
-    phi[S::N - 1] = 1.0 - sph;
-#pragma unroll
-    for (int l = 0; l < S::N; ++l) rl[l] = (double)Ut[S::cA(l)] / phi[l];
-    double ke = 0.0;
-#pragma unroll
-    for (int a = 0; a < S::D; ++a) ke += (double)Ut[S::cM(a)] * (double)Ut[S::cM(a)] / rho;
-    const double p = mix_pressure<S>(P, phi, rl, J2, (double)Ut[S::cE] - 0.5 * ke);
-    double c2, G, sY;
-    mix_c2_G<S>(P, phi, rl, J2, p, c2, G, sY);
-    const double Hn = sqrt(J2);
-    const double seq = 2.449489742783178 * G * Hn;
-    if (sY > 0.0 && seq > sY) {
-      const double s = sY / seq;
-      double E[9], Vn[9];
-      plastic_exp(s - 1.0, H, E);
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) Vn[3 * a + b] = E[3 * a] * V[b] + E[3 * a + 1] * V[3 + b] + E[3 * a + 2] * V[6 + b];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) V[q] = Vn[q];
-      const int sp = P.solid_phase;
-      const double as = pick<S::N>(phi, sp) * pick<S::N>(rl, sp);
-      Uc[S::cEP] = (T)((double)Uc[S::cEP] + as * 0.816496580927726 * (1.0 - s) * Hn);
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Uc[S::cV(0, 0) + q] = (T)V[q];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) U[(S::cV(0, 0) + q) * P.fs + c] = Uc[S::cV(0, 0) + q];
-    U[S::cEP * P.fs + c] = Uc[S::cEP];
-  }
-  wave_count_add(&sc->surr_net, used_net);
-  wave_count_add(&sc->surr_exact, used_exact);
-  if (stage == 2) {
-    double rate = 0.0;
-    if (in) {
-      if (!act) load_cons<S>(P, U, c, Uc);
-      if (!((double)Uc[S::R] > 0.5)) {
-        int pi[3];
-        decode(P, c, pi[0], pi[1], pi[2]);
-        double x[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < S::D; ++a) x[a] = P.x0[a] + (pi[a] + 0.5) * P.dx[a];
-        const double tc = sc->t[A.par] - sc->t_motion;
-        rate = cfl_rate<S>(P, Uc, x, tc + sc->dtv[A.par]);
+        for (int q = 0; q < 9; ++q) V[q] *= scl;
       }
+      // cells that provably do not yield keep V (renormalised) and skip the
+      // closure; a wavefront without any other cell skips the network
+      const bool ret = act && P.plastic && may_yield<S>(P, Un, V);
+      const StrainInv si = strain_invariants(V);
+      const bool env = ret && si.tau <= m.tau_max;
+      float z[6] = {0, 0, 0, 0, 0, 0}, y[6] = {0, 0, 0, 0, 0, 0};
+      if (env) mlp_features(si, m.tau_max, z);
+      if (__any(env)) mlp_wave_forward(m, L, z, y);  // every lane of the wavefront
+      int used_net = 0, used_exact = 0;
+      if (ret) {
+        double H[9], J2 = 0.0;
+        bool ok = env;
+        if (ok) {
+          double a[3], cc[3];
+          mlp_decode(si, y, a, cc);
+          const SymM& X = si.X;
+          const SymM& X2 = si.X2;
+          const double h00 = a[0] + a[1] * X.a00 + a[2] * X2.a00, h11 = a[0] + a[1] * X.a11 + a[2] * X2.a11;
+          const double h22 = a[0] + a[1] * X.a22 + a[2] * X2.a22, h01 = a[1] * X.a01 + a[2] * X2.a01;
+          const double h02 = a[1] * X.a02 + a[2] * X2.a02, h12 = a[1] * X.a12 + a[2] * X2.a12;
+          H[0] = h00; H[1] = h01; H[2] = h02; H[3] = h01; H[4] = h11; H[5] = h12; H[6] = h02; H[7] = h12; H[8] = h22;
+          const double j2h = h00 * h00 + h11 * h11 + h22 * h22 + 2.0 * (h01 * h01 + h02 * h02 + h12 * h12);
+          // J2 = tr(H^2) from the network's H^2 coefficients (tr X^2 = tau^2)
+          J2 = 3.0 * cc[0] + cc[1] * si.e1 + cc[2] * si.tau * si.tau;
+          ok = fabs(J2 - j2h) <= 1e-6 * j2h + 1e-300;
+          // tr H = 3 a0 + a1 tr X + a2 tr X^2 must vanish (unit determinant)
+          ok = ok && fabs(h00 + h11 + h22) <= 1e-6 * sqrt(j2h) + 1e-300;
+          J2 = j2h;
+        }
+        if (!ok) hencky3(V, H, J2);
+        used_net = ok ? 1 : 0;
+        used_exact = ok ? 0 : 1;
+        // closure terms of the plastic return: phases, pressure, G, yield
+        double rho = 0.0;
+#pragma unroll
+        for (int l = 0; l < S::N; ++l) rho += (double)Un[S::cA(l)];
+        double phi[kMaxMat], rl[kMaxMat], sph = 0.0;
+#pragma unroll
+        for (int l = 0; l < S::N - 1; ++l) {
+          phi[l] = (double)Un[S::cPHI(l)];
+          sph += phi[l];
+        }
+        phi[S::N - 1] = 1.0 - sph;
+#pragma unroll
+        for (int l = 0; l < S::N; ++l) rl[l] = (double)Un[S::cA(l)] / phi[l];
+        double ke = 0.0;
+#pragma unroll
+        for (int a = 0; a < S::D; ++a) ke += (double)Un[S::cM(a)] * (double)Un[S::cM(a)] / rho;
+        const double p = mix_pressure<S>(P, phi, rl, J2, (double)Un[S::cE] - 0.5 * ke);
+        double c2, G, sY;
+        mix_c2_G<S>(P, phi, rl, J2, p, c2, G, sY);
+        const double Hn = sqrt(J2);
+        const double seq = 2.449489742783178 * G * Hn;
+        if (sY > 0.0 && seq > sY) {
+          const double s = sY / seq;
+          double E[9], Vn[9];
+          plastic_exp(s - 1.0, H, E);
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Vn[3 * a + b] = E[3 * a] * V[b] + E[3 * a + 1] * V[3 + b] + E[3 * a + 2] * V[6 + b];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) V[q] = Vn[q];
+          const int sp = P.solid_phase;
+          const double as = pick<S::N>(phi, sp) * pick<S::N>(rl, sp);
+          Un[S::cEP] = (T)((double)Un[S::cEP] + as * 0.816496580927726 * (1.0 - s) * Hn);
+        }
+      }
+      if (act) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Un[S::cV(0, 0) + q] = (T)V[q];
+      }
+      wave_count_add(&sc->surr_net, used_net);
+      wave_count_add(&sc->surr_exact, used_exact);
     }
-    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
-    if (lane == 0) cflpart[(size_t)blockIdx.x * 4 + wave] = rate;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->npart = gridDim.x * 4;
   }
+};
+
+// The final x sweep with the surrogate sources. LDS per wavefront: the
+// streamed d, then (once d has been read back) the network's tile.
+template <class S, typename T>
+union XSurrLds {
+  T d[S::NF * kWave];
+  MlpWaveLds mlp;
+};
+
+template <class S, typename T, bool MB = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x_surr(
+    Params P, const T* __restrict__ Uin, const T* __restrict__ U0, const T* __restrict__ Dacc, T* __restrict__ Uout,
+    DevScalars* __restrict__ sc, double* __restrict__ cflpart, StepArgs A, double bcoef, int stage, MlpDev m) {
+  __shared__ XSurrLds<S, T> lds[kMaxWPB];
+  const int wpb = blockDim.x / kWave;
+  const long long blin = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
+  XSurrLds<S, T>* my = &lds[threadIdx.x / kWave];
+  SurrogateSources src{m, &my->mlp, sc};
+  sweep_x_body<S, T, SurrogateSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x,
+                                           blockIdx.y, blockIdx.z, blin, wpb, nparts, my->d, src);
 }
 
 }  // namespace rbdi

@@ -14,6 +14,7 @@ namespace rbdi {
 
 constexpr int kMaxF = 20;
 constexpr int kMaxMat = 2;
+constexpr int kMaxBody = 4;  // rigid bodies with their own motions
 
 enum { EOS_IDEAL = 0, EOS_STIFFENED = 1, EOS_ROMENSKII = 2 };
 enum { BC_TRANSMISSIVE = 0, BC_REFLECTIVE = 1, BC_DIRICHLET = 2, BC_PERIODIC = 3 };
@@ -65,10 +66,16 @@ struct Params {
   int solid_phase;
   int r_static;           // rigid velocity identically zero: r never changes
   int stiff;              // some phase has a stiffening energy (B(phi) != 0)
-  int surr;               // elastoplastic sources (and the CFL partials of the
-                          // last stage) by the separate surrogate pass
+  int surr;               // elastoplastic sources with the surrogate network
+                          // (the final sweep's variant with the network)
   MatDev mat[kMaxMat];
-  double vr[3], om[3], ctr[3];
+  // Rigid motions v + omega x (x - c): body 0 everywhere, except where a
+  // point lies in the ownership box of a body 1..nbody-1 (first match); the
+  // centres and boxes are those of the time the motions were set and move
+  // with each body's translation.
+  int nbody;
+  double vr[kMaxBody][3], om[kMaxBody][3], ctr[kMaxBody][3];
+  double blo[kMaxBody][3], bhi[kMaxBody][3];
   double bcW[6][kMaxF];   // Dirichlet primitive states per face
 };
 
@@ -917,11 +924,55 @@ struct HllcFace {
 // Rigid-body velocity and seeding states (Sec. 2.3, Sec. 3.2)
 // ---------------------------------------------------------------------------
 
-__device__ inline void rigid_velocity(const Params& P, const double x[3], double v[3]) {
-  const double d0 = x[0] - P.ctr[0], d1 = x[1] - P.ctr[1], d2 = x[2] - P.ctr[2];
-  v[0] = P.vr[0] + P.om[1] * d2 - P.om[2] * d1;
-  v[1] = P.vr[1] + P.om[2] * d0 - P.om[0] * d2;
-  v[2] = P.vr[2] + P.om[0] * d1 - P.om[1] * d0;
+// Rigid velocity of body B at point x, tc after the motion was set: the
+// body's centre has moved by v tc since, which is evaluated as x - v tc
+// against the centre of that time.
+template <int B>
+__device__ inline void body_velocity(const Params& P, const double x[3], double tc, double v[3]) {
+  const double xs0 = x[0] - P.vr[B][0] * tc, xs1 = x[1] - P.vr[B][1] * tc, xs2 = x[2] - P.vr[B][2] * tc;
+  const double d0 = xs0 - P.ctr[B][0], d1 = xs1 - P.ctr[B][1], d2 = xs2 - P.ctr[B][2];
+  v[0] = P.vr[B][0] + P.om[B][1] * d2 - P.om[B][2] * d1;
+  v[1] = P.vr[B][1] + P.om[B][2] * d0 - P.om[B][0] * d2;
+  v[2] = P.vr[B][2] + P.om[B][0] * d1 - P.om[B][1] * d0;
+}
+
+template <int B>
+__device__ inline bool body_owns(const Params& P, const double x[3], double tc) {
+  const double xs0 = x[0] - P.vr[B][0] * tc, xs1 = x[1] - P.vr[B][1] * tc, xs2 = x[2] - P.vr[B][2] * tc;
+  return (xs0 >= P.blo[B][0]) & (xs0 < P.bhi[B][0]) & (xs1 >= P.blo[B][1]) & (xs1 < P.bhi[B][1]) &
+         (xs2 >= P.blo[B][2]) & (xs2 < P.bhi[B][2]);
+}
+
+// Body B's claim on x: its velocity replaces v where no earlier body has
+// claimed x and x lies in B's ownership box. Both candidates are computed and
+// selected, without branches: branches that differ only in the body's
+// offsets into the launch parameters get merged into one load through a
+// chosen address, which copies the parameters to scratch memory.
+template <int B>
+__device__ inline void claim_body(const Params& P, const double x[3], double tc, double v[3], bool& taken) {
+  double w[3];
+  body_velocity<B>(P, x, tc, w);
+  const bool own = !taken && B < P.nbody && body_owns<B>(P, x, tc);
+  v[0] = own ? w[0] : v[0];
+  v[1] = own ? w[1] : v[1];
+  v[2] = own ? w[2] : v[2];
+  taken = taken || own;
+}
+
+// Rigid velocity at point x (Sec. 2.3: v_r = v + omega x (x - c) of the body
+// that owns x: the first body 1.. whose ownership box holds x, else body 0).
+// MB = false: body 0 only, for launches with one body (the claims cost the
+// sweeps registers even where the run-time test skips them).
+template <bool MB>
+__device__ inline void rigid_velocity(const Params& P, const double x[3], double tc, double v[3]) {
+  static_assert(kMaxBody == 4, "one claim per body");
+  body_velocity<0>(P, x, tc, v);
+  if (MB && P.nbody > 1) {
+    bool taken = false;
+    claim_body<1>(P, x, tc, v, taken);
+    claim_body<2>(P, x, tc, v, taken);
+    claim_body<3>(P, x, tc, v, taken);
+  }
 }
 
 // Mirror state of the seeding routine, as the Householder reflection
@@ -1067,6 +1118,47 @@ __device__ inline void plastic_exp(double a, const double* H, double* E) {
   E[5] = E[7] = c1 * A.a12 + c2 * A2.a12;
 }
 
+// Whether the radial return may act on a cell: false when it provably does
+// not. For X = Vbar Vbar^T - I with tau = |X|_F < 1 every eigenvalue x of X
+// has |x| <= tau and |ln(1 + x)| <= |x| / (1 - |x|), so the Hencky strain
+// obeys |H|_F <= tau / (2 (1 - tau)); with the mixture G and yield stress
+// (neither depends on the strain) sigma_eq = sqrt(6) G |H|_F then stays at
+// or below sqrt(6) G tau / (2 (1 - tau)). When that bound (1% margin for
+// rounding) is at most sigma_Y, or sigma_Y = 0, the return is not applied,
+// exactly as the full test would decide, so the cell skips the closure.
+template <class S, typename T>
+__device__ inline bool may_yield(const Params& P, const T* U, const double* V) {
+  double phi[kMaxMat], s = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N - 1; ++l) {
+    phi[l] = (double)U[S::cPHI(l)];
+    s += phi[l];
+  }
+  phi[S::N - 1] = 1.0 - s;
+  double nG = 0.0, nY = 0.0, den = 0.0;
+#pragma unroll
+  for (int l = 0; l < S::N; ++l) {
+    const MatDev& m = P.mat[l];
+    if (m.kind == EOS_ROMENSKII) {
+      const double rho = (double)U[S::cA(l)] / phi[l];
+      nG += phi[l] * m.G0 * pow_small(rho * m.invrho0, m.ibeta1, m.beta + 1.0) * m.invGam;
+    }
+    nY += phi[l] * m.sigY * m.invGam;
+    den += phi[l] * m.invGam;
+  }
+  if (!(nY > 0.0)) return false;  // sigma_Y = 0: no return
+  const double x00 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2] - 1.0;
+  const double x11 = V[3] * V[3] + V[4] * V[4] + V[5] * V[5] - 1.0;
+  const double x22 = V[6] * V[6] + V[7] * V[7] + V[8] * V[8] - 1.0;
+  const double x01 = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
+  const double x02 = V[0] * V[6] + V[1] * V[7] + V[2] * V[8];
+  const double x12 = V[3] * V[6] + V[4] * V[7] + V[5] * V[8];
+  const double tau = sqrt(x00 * x00 + x11 * x11 + x22 * x22 + 2.0 * (x01 * x01 + x02 * x02 + x12 * x12));
+  if (!(tau < 0.5)) return true;
+  // sqrt(6) G tau / (2 (1 - tau)) > sigma_Y, both sides times den > 0
+  return 1.01 * 2.449489742783178 * nG * tau > 2.0 * (1.0 - tau) * nY;
+}
+
 template <class S, typename T>
 __device__ inline void solid_sources(const Params& P, T* U) {
   double V[9];
@@ -1077,7 +1169,7 @@ __device__ inline void solid_sources(const Params& P, T* U) {
   const double sc = 1.0 / cbrt(det);
 #pragma unroll
   for (int q = 0; q < 9; ++q) V[q] *= sc;
-  if (P.plastic) {
+  if (P.plastic && may_yield<S>(P, U, V)) {
     T Ut[S::NF], Wt[S::NF];
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) Ut[q] = U[q];

@@ -49,6 +49,10 @@ class Problem:
     v_r: tuple = (0.0, 0.0, 0.0)
     omega: tuple = (0.0, 0.0, 0.0)
     center: tuple = (0.0, 0.0, 0.0)
+    # further rigid bodies with their own motion, each a dict with v, omega,
+    # center and its ownership box box_lo, box_hi (3-tuples); v_r, omega and
+    # center above are body 0's, which moves every point no box claims
+    bodies: tuple = ()
     recon: str = "bvd_thinc"
     riemann: str = "hllc"
     seed: str = "original"
@@ -59,6 +63,14 @@ class Problem:
     lm_mach: float = 0.1
     cfl: float = 0.4
     t_end: float = 0.0
+
+    def body_table(self):
+        """(v, omega, center, box_lo, box_hi), each (1 + len(bodies)) x 3,
+        body 0 first (its box row unused)."""
+        rows = [dict(v=self.v_r, omega=self.omega, center=self.center, box_lo=(0.0,) * 3, box_hi=(0.0,) * 3)]
+        rows += list(self.bodies)
+        return tuple(np.array([r[k] for r in rows], dtype=np.float64)
+                     for k in ("v", "omega", "center", "box_lo", "box_hi"))
 
     @property
     def nmat(self):
@@ -239,11 +251,12 @@ def air_water(nx=2048, ny=1024, eps=1e-6):
                    center=(0.25, 0.25, 0.0), recon="bvd_thinc", riemann="hllc", cfl=0.4, t_end=4.8e-3)
 
 
-def copper_indenter(n=256, eps=1e-6, L=25.6e-3):
+def copper_indenter(n=256, eps=1e-6, L=25.6e-3, gap=None):
     """3D copper block (z < L/2, Romenskii, rho0 8930, G0 46 GPa, perfect
     plasticity 0.12 GPa) under air, with a flat-ended rigid cylinder (axis z at
-    the centre, radius 20/256 of the side, flat end 0.1 mm above the copper)
-    moving at -200 m/s along z."""
+    the centre, radius 20/256 of the side) moving at -200 m/s along z. The flat
+    end starts `gap` above the copper surface (default L/256 = 0.1 mm; a
+    negative gap starts it that far inside the copper, in contact)."""
     h = L / n
     X, Y, Z = _mesh((n, n, n), (h, h, h), (0.0, 0.0, 0.0))
     cu = dict(TABLE1["copper"])
@@ -261,7 +274,7 @@ def copper_indenter(n=256, eps=1e-6, L=25.6e-3):
         W[7 + 4 * a] = 1.0   # Vbar = I
     W[16] = 0.0              # eps_p
     R = L * 20.0 / 256.0
-    z_end = zc + L / 256.0
+    z_end = zc + (L / 256.0 if gap is None else gap)
     rad = np.sqrt((X - 0.5 * L) ** 2 + (Y - 0.5 * L) ** 2)
     sdf = np.maximum(rad - R, z_end - Z)
     mats = [romenskii(cu["rho0"], cu["K0"], cu["G0"], cu["alpha"], cu["beta"], cu["Gamma0"], 0.12e9),
@@ -272,6 +285,51 @@ def copper_indenter(n=256, eps=1e-6, L=25.6e-3):
                        "transmissive"],
                    W0=W, sdf=sdf, width=1.0, v_r=(0.0, 0.0, -200.0), center=(0.5 * L, 0.5 * L, z_end),
                    recon="bvd_thinc", riemann="hllc", cfl=0.3, t_end=2.5e-6)
+
+
+def extrusion(nx=2048, ny=1728, eps=1e-6, x_block=100e-3, box_cells=12):
+    """2D extrusion of an aluminium block by a piston through a rigid wedge
+    (Sec. 4.5): x in [-21, 120] mm, y in [0, 120] mm, reflective walls at
+    y = 0 and y = 120 mm, transmissive x faces. Aluminium of Table 1 with
+    perfect plasticity at 0.2976 GPa fills the channel from the piston to
+    x = x_block (air, gamma 1.4, beyond), at rest, p = 1e5 Pa. Two rigid
+    bodies share the r field (union of signed distances): body 0 the static
+    wedge, the region below the line from (0, 0) at 15 degrees to the x
+    axis; body 1 the piston x < -20 mm, moving at 100 m/s along x, owning
+    the points left of box_cells cells in front of its face (the box moves
+    with it). The default grid is the finest level of the 256 x 216 base
+    grid with three refinements by 2, as a uniform grid; t_end = 20 us,
+    CFL 0.4."""
+    x0, x1, y1 = -21e-3, 120e-3, 120e-3
+    dx = (x1 - x0) / nx
+    dy = y1 / ny
+    X, Y, _ = _mesh((nx, ny, 1), (dx, dy, 1.0), (x0, 0.0, 0.0))
+    al = TABLE1["aluminium"]
+    phi_al = eps + (1.0 - 2.0 * eps) * 0.5 * (1.0 - np.tanh((X - x_block) / dx))
+    W = np.zeros((17, 1, ny, nx))
+    W[0] = phi_al            # phi_Al
+    W[1] = al["rho0"]        # rho_Al
+    W[2] = 1.2               # rho_air
+    W[3:5] = 0.0             # u, v
+    W[5] = 1.0e5             # p
+    for a in range(3):
+        W[6 + 4 * a] = 1.0   # Vbar = I
+    W[15] = 0.0              # eps_p
+    th = math.radians(15.0)
+    x_piston = -20e-3
+    sdf_wedge = math.cos(th) * Y - math.sin(th) * X
+    sdf_piston = X - x_piston
+    sdf = np.minimum(sdf_wedge, sdf_piston)
+    inf = math.inf
+    piston = dict(v=(100.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0), center=(x_piston, 0.5 * y1, 0.0),
+                  box_lo=(-inf, -inf, -inf), box_hi=(x_piston + box_cells * min(dx, dy), inf, inf))
+    mats = [romenskii(al["rho0"], al["K0"], al["G0"], al["alpha"], al["beta"], al["Gamma0"], 0.2976e9),
+            ideal(1.4)]
+    return Problem(name="extrusion", dim=2, n=(nx, ny, 1), dx=(dx, dy, 1.0), origin=(x0, 0.0, 0.0),
+                   materials=mats, solid=True,
+                   bc=["transmissive", "transmissive", "reflective", "reflective", "transmissive", "transmissive"],
+                   W0=W, sdf=sdf, width=1.0, v_r=(0.0, 0.0, 0.0), center=(0.0, 0.0, 0.0), bodies=(piston,),
+                   recon="bvd_thinc", riemann="hllc", cfl=0.4, t_end=20e-6)
 
 
 def batch(count=64, seed=2111, nmin=128, nmax=512, steps=200):
@@ -348,6 +406,20 @@ def piston_1d(n=400, v_p=1.0, x_p=0.2, t_end=0.3, recon="muscl"):
                    materials=[ideal(1.4)], solid=False, bc=["transmissive"] * 6, W0=W, sdf=sdf, width=1.0,
                    v_r=(v_p, 0.0, 0.0), center=(x_p, 0.0, 0.0), recon=recon, riemann="hllc", cfl=0.5,
                    t_end=t_end)
+
+
+def piston_wall_1d(n=800, v_p=1.0, x_p=0.2, x_w=0.8, t_end=0.4, box_cells=20, recon="muscl"):
+    """Gas at rest (1, 0, 1) between two rigid bodies with their own motion:
+    a piston x < x_p moving at v_p (body 1, owning the points behind its box
+    face box_cells cells ahead of it) and a static wall x > x_w (body 0)."""
+    p = piston_1d(n, v_p=v_p, x_p=x_p, t_end=t_end, recon=recon)
+    x = (np.arange(n) + 0.5) / n
+    p.name = "piston_wall"
+    p.sdf = np.minimum(x - x_p, x_w - x).reshape(1, 1, n)
+    p.v_r, p.center = (0.0, 0.0, 0.0), (x_w, 0.0, 0.0)
+    p.bodies = (dict(v=(v_p, 0.0, 0.0), omega=(0.0, 0.0, 0.0), center=(x_p, 0.0, 0.0),
+                     box_lo=(-math.inf,) * 3, box_hi=(x_p + box_cells / n, math.inf, math.inf)),)
+    return p
 
 
 def quiescent_body(nx=64, ny=48, recon="bvd_thinc", riemann="hllc", seed="original"):

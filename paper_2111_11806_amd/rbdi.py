@@ -66,7 +66,7 @@ _lib = None
 
 EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rbdi_set_material",
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
-           "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_compute_dt",
+           "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_set_rigid_bodies", "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
            "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
            "rbdi_set_x_waves", "rbdi_autotune",
@@ -105,6 +105,7 @@ def load():
         getattr(L, nm).argtypes = [vp, vp, ip]
     L.rbdi_set_rigid_sdf.argtypes = [vp, vp, ip, ctypes.c_double, dp, dp, dp]
     L.rbdi_set_rigid_motion.argtypes = [vp, dp, dp, dp]
+    L.rbdi_set_rigid_bodies.argtypes = [vp, ip, dp, dp, dp, dp, dp]
     L.rbdi_compute_dt.argtypes = [vp, ctypes.c_double, dp]
     L.rbdi_step.argtypes = [vp, ctypes.c_double]
     L.rbdi_advance.argtypes = [vp, ctypes.c_double, ip, ctypes.c_double]
@@ -215,6 +216,8 @@ class Solver:
         self.set_state_prim(prob.W0)
         if prob.sdf is not None:
             self.set_rigid_sdf(prob.sdf, prob.width, prob.v_r, prob.omega, prob.center)
+        if prob.bodies:
+            self.set_rigid_bodies(*prob.body_table())
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -266,6 +269,15 @@ class Solver:
 
     def set_rigid_motion(self, v, omega, center):
         _check(load().rbdi_set_rigid_motion(self._h, _dp(_arr(v, 3)), _dp(_arr(omega, 3)), _dp(_arr(center, 3))))
+
+    def set_rigid_bodies(self, v, omega, center, box_lo, box_hi):
+        """Motions of several bodies: rows of v, omega, center (body 0 moves
+        every point no other body owns) and of the ownership boxes
+        [box_lo, box_hi) of bodies 1.. (row 0 ignored)."""
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+        nb = v.shape[0]
+        a = [np.ascontiguousarray(x, dtype=np.float64).reshape(nb, 3) for x in (v, omega, center, box_lo, box_hi)]
+        _check(load().rbdi_set_rigid_bodies(self._h, nb, *[_dp(x) for x in a]))
 
     def compute_dt(self, cfl):
         out = ctypes.c_double()
