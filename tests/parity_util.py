@@ -52,6 +52,121 @@ def rel_linf(a, b):
     return np.abs(a - b).max(axis=1) / scale
 
 
+# Bars of the per-field comparisons (relative L1, relative Linf). The FP32
+# Linf bar allows a shock to sit a small fraction of a cell apart after a few
+# hundred FP32 steps (pointwise jump x position difference).
+BARS = {"fp64": (1e-10, 1e-8), "fp32": (1e-4, 5e-3)}
+# A component of a vector or tensor (momentum, stretch) whose norm is below
+# FLOOR times the mean norm of its family's components is judged against that
+# floor instead of its own norm: shear stretches (~1e-3 next to diagonal
+# entries ~1) and transverse momenta near rest carry the absolute rounding
+# of their O(1) siblings, which their own tiny norm would magnify.
+FLOOR = 1e-2
+
+
+def families(names):
+    """Index lists of the vector / tensor each field belongs to."""
+    mom = [i for i, n in enumerate(names) if n in ("mx", "my", "mz", "u", "v", "w")]
+    ten = [i for i, n in enumerate(names) if n.startswith("V") and len(n) == 3]
+    return [mom if i in mom else ten if i in ten else [i] for i in range(len(names))]
+
+
+def field_errors(a, b, names):
+    """Per field: relative L1 and relative Linf, each over the larger of the
+    field's own norm and FLOOR times its family's mean norm; a field whose
+    family is zero everywhere in the reference is reported as its mean and
+    maximum absolute difference. Also the raw relative L1 (own norm)."""
+    a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
+    d = np.abs(a - b)
+    l1 = d.sum(axis=1)
+    n1 = np.abs(b).sum(axis=1)
+    ninf = np.abs(b).max(axis=1)
+    dinf = d.max(axis=1)
+    out = {}
+    for q, fam in enumerate(families(names)):
+        den1 = max(n1[q], FLOOR * n1[fam].mean())
+        deninf = max(ninf[q], FLOOR * ninf[fam].max())
+        e1 = l1[q] / den1 if den1 > 0 else l1[q] / a.shape[1]
+        einf = dinf[q] / deninf if deninf > 0 else dinf[q]
+        raw = l1[q] / n1[q] if n1[q] > 0 else l1[q] / a.shape[1]
+        out[names[q]] = (float(e1), float(einf), float(raw))
+    return out
+
+
+# FP32 storage of a stiff solid's mass and volume fraction sets a floor under
+# the momentum error of the FP32 elastoplastic path: one FP32 ulp of the
+# copper density (K0 = 130 GPa) is ~8 kPa of pressure. The CPU oracle with
+# its stored state rounded to FP32 after every step (nothing else changed)
+# already reaches 1.7e-4 relative L1 on the momentum along the indentation
+# (tests/test_fp32_storage_floor.py); the FP32 elastoplastic momenta are held
+# to 3e-4 instead of 1e-4, every other field to the FP32 bars.
+FP32_SOLID_MOMENTUM = {m: (3e-4, 5e-3) for m in ("mx", "my", "mz")}
+# Through the contact of the punch the same storage floor rises to a few 1e-3
+# in the momenta, the energy, the stretch and the plastic strain
+# (tests/test_fp32_storage_floor.py: FP32 storage alone, FP64 arithmetic,
+# 64^3 through contact); the FP32 elastoplastic path is held there to 1e-2
+# in L1 and 1e-1 in Linf on every field, over the non-rigid cells (rigid
+# cells hold seeded ghost states, which a probe decision taken on FP32 r
+# may change as a whole).
+FP32_SOLID_CONTACT = {n: (1e-2, 1e-1) for n in
+                      ["arho0", "arho1", "mx", "my", "mz", "E", "phi0", "aeps", "r"] +
+                      ["V%d%d" % (a, b) for a in range(3) for b in range(3)]}
+
+
+# Long runs through the punch's contact amplify rounding: the oracle against
+# itself, with one ulp of noise added to its stored state after every step,
+# drifts from 1e-11 at the contact (0.5 us) to ~1e-3 relative L1 in the
+# momenta at 2.5 us on the 64^3 copper indenter, growing by ~30x every five
+# steps from 1.1 us on (plastic flow under the punch; BVD's choice between
+# its two candidates flips on rounding and each flip seeds others). No
+# implementation with another rounding order can follow the oracle closer
+# than that. Such runs are compared in two ways: every step's operator on
+# the oracle's own state at checkpoints (to the FP64 bars), and the whole
+# run against FLOOR_FACTOR times the error of a perturbed oracle run of the
+# same length (ulp noise for FP64, FP32 rounding of the stored state for
+# FP32).
+FLOOR_FACTOR = 3.0
+
+
+def ulp_noise(U, rng):
+    """U with each value moved by -1, 0 or +1 ulp (relative 2^-52)."""
+    return U * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 0.0, 1.0], size=U.shape))
+
+
+def fp32_rounded(U):
+    return np.asarray(U).astype(np.float32).astype(np.float64)
+
+
+def floor_bars(floor_err, precision, factor=FLOOR_FACTOR):
+    """Per-field (L1, Linf) bars: the larger of the precision's bars and
+    factor times a floor run's errors (field_errors of a perturbed oracle)."""
+    l1b, linfb = BARS[precision]
+    return {k: (max(l1b, factor * v[0]), max(linfb, factor * v[1])) for k, v in floor_err.items()}
+
+
+def non_rigid(a, b, names):
+    """a and b with the cells that are rigid (r > 0.5) in b set to zero."""
+    keep = np.asarray(b)[names.index("r")] <= 0.5
+    return np.where(keep, a, 0.0), np.where(keep, b, 0.0)
+
+
+def check_fields(a, b, names, precision="fp64", label="", bars=None, field_bars=None):
+    """Assert the per-field bars of `precision` (or explicit (l1, linf)
+    bars, and per-field exceptions field_bars {name: (l1, linf)}) and print
+    every field's L1 / Linf."""
+    l1b, linfb = bars if bars is not None else BARS[precision]
+    fb = field_bars or {}
+    err = field_errors(a, b, names)
+    announce("  %s per field L1/Linf (bars %.0e/%.0e%s): " % (
+        label, l1b, linfb, "; " + ", ".join("%s %.0e" % (k, v[0]) for k, v in fb.items()) if fb else "") +
+        ", ".join("%s %.1e/%.1e" % (k, v[0], v[1]) for k, v in err.items()))
+    bad = {k: v for k, v in err.items()
+           if not (v[0] <= fb.get(k, (l1b, linfb))[0] and v[1] <= fb.get(k, (l1b, linfb))[1])}
+    assert not bad, bad
+    return err
+
+
 def announce(msg):
     """Print and flush the case name before a GPU step."""
     sys.stdout.write("\n[gpu case] %s\n" % msg)
@@ -64,3 +179,8 @@ def gpu_available():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def progress(label):
+    """A progress callback for long oracle runs (prints steps and time)."""
+    return lambda k, t: announce("  %s: oracle at step %d, t = %.4g" % (label, k, t))

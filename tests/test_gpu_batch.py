@@ -4,21 +4,20 @@ instances of uneven sizes advanced by one launch per phase.
 - batched == single-instance, bitwise (same per-cell arithmetic);
 - bitwise identical across launch shapes (tile width, block size, persistent
   grid, XCD ranges) and after autotuning, which leaves the states unchanged;
-- instance-wise parity with the CPU FP64 oracle (FP64 <= 1e-10, FP32 <= 1e-4
-  relative L1 per conserved field), on small batches and on sampled members
-  of the full 64-instance batch (seed 2111, sizes in {128..512}^2).
+- instance-wise parity with the CPU FP64 oracle (relative L1 and Linf per
+  conserved field, parity_util.BARS), on small batches and on every member
+  of the full 64-instance batch (seed 2111, sizes in {128..512}^2) after
+  100 steps and over the benchmark's 200th step.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_2111_11806_amd import inputs
-from parity_util import announce, rel_l1
+from parity_util import announce, check_fields, field_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-10
-TOL32 = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +82,7 @@ def test_batch_elvira_members_vs_oracle(rbdi):
         orc = oracle.Oracle(p)
         orc.run(nsteps=15)
         assert abs(orc.t - st[k]["t"]) <= 1e-12 * orc.t
-        assert np.all(rel_l1(bat[k], orc.get_state_cons()) <= TOL64)
+        check_fields(bat[k], orc.get_state_cons(), p.cons_names(), "fp64", p.name)
 
 
 def test_batch_fixed_dt_equals_single_bitwise(rbdi):
@@ -145,8 +144,8 @@ def test_batch_members_refuse_own_steps(rbdi):
     sv[0].step(1e-4)  # free again
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
-def test_batch_vs_oracle_small(rbdi, precision, tol):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_vs_oracle_small(rbdi, precision):
     probs = _small(count=5, seed=2111, nmin=32, nmax=100)
     nsteps = 25
     dts = []
@@ -159,40 +158,76 @@ def test_batch_vs_oracle_small(rbdi, precision, tol):
     bat, st, _ = _run_batch(rbdi, probs, precision, nsteps, dts=dts)
     for k, o in enumerate(orcs):
         assert st[k]["nonphysical"] == 0
-        rl = rel_l1(bat[k], o.get_state_cons())
-        assert np.all(rl <= tol), (probs[k].name, rl)
+        check_fields(bat[k], o.get_state_cons(), probs[k].cons_names(), precision, probs[k].name)
 
 
-def test_batch_full_size_sampled_vs_oracle_fp32(rbdi):
-    """The full 64-instance batch (seed 2111, FP32) for 200 steps: three
-    members (smallest, median, largest) take the oracle's dt list and are
-    compared with it; the others take their own device CFL dt. Every member
-    stays admissible."""
+def test_batch_full_size_vs_oracle_fp32(rbdi):
+    """The full 64-instance batch (seed 2111, FP32), autotuned, every member
+    on its oracle's dt list, compared per conserved field with the FP32 bars:
+    after 100 steps from the start, and over the benchmark's last step (step
+    200, from the oracle's state after 199 steps, in a second batch).
+    Beyond ~100 steps the shocks reach the bodies and the wakes amplify
+    FP32 rounding (the oracle itself, perturbed by FP32-sized noise each
+    step, parts from its unperturbed run by up to 5e-4 in the transverse
+    momentum by step 200); the 200-step states are reported, not held to the
+    FP32 bars."""
     probs = inputs.batch()
     sizes = np.array([p.ncells for p in probs])
-    order = np.argsort(sizes)
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
-    nsteps = 200
-    orcs = {}
-    dts = [[] for _ in probs]
-    for k in pick:
-        o = oracle.Oracle(probs[k])
-        dts[k] = o.run(nsteps=nsteps)
-        orcs[k] = o
-    announce("full batch fp32, %d instances, %d cells, sampled %s" % (len(probs), sizes.sum(), pick))
+    announce("full batch: oracles of %d instances, %d cells, 200 steps" % (len(probs), sizes.sum()))
+    U100, U199, U200, dts = [], [], [], []
+    for k, p in enumerate(probs):
+        o = oracle.Oracle(p)
+        d = o.run(nsteps=100)
+        U100.append(o.get_state_cons())
+        d += o.run(nsteps=99)
+        U199.append(o.get_state_cons())
+        d += o.run(nsteps=1)
+        U200.append(o.get_state_cons())
+        dts.append(d)
+        del o
+        if k % 8 == 7:
+            announce("  oracles done: %d of %d" % (k + 1, len(probs)))
+    names = probs[0].cons_names()
+
+    def compare(sv, refs, label):
+        worst = {}
+        for k, s in enumerate(sv):
+            assert s.status()["nonphysical"] == 0, (k, label)
+            err = check_fields(s.get_state_cons(), refs[k], names, "fp32",
+                               "%s %s n=%s" % (label, probs[k].name, probs[k].n[:2]))
+            for q, v in err.items():
+                worst[q] = max(worst.get(q, (0, 0, 0)), v)
+        announce("  %s, worst over the 64 members: " % label +
+                 ", ".join("%s %.1e/%.1e" % (q, v[0], v[1]) for q, v in worst.items()))
+
+    announce("full batch fp32, 64 instances, steps 1-100")
     sv = [rbdi.Solver(p, "fp32") for p in probs]
     b = rbdi.Batch(sv)
     b.autotune(reps=2)
-    for s in range(nsteps):
-        b.step([d[s] if d else 0.0 for d in dts], probs[0].cfl)
+    for s in range(100):
+        b.step([d[s] for d in dts], probs[0].cfl)
+    compare(sv, U100, "100 steps")
+    for s in range(100, 200):
+        b.step([d[s] for d in dts], probs[0].cfl)
     for k, s in enumerate(sv):
         st = s.status()
-        assert st["nonphysical"] == 0 and st["steps"] == nsteps, (k, st)
-    for k in pick:
-        rl = rel_l1(sv[k].get_state_cons(), orcs[k].get_state_cons())
-        announce("  %s n=%s rel L1 %s" % (probs[k].name, probs[k].n[:2], np.array2string(rl, precision=2)))
-        assert np.all(rl <= TOL32), (probs[k].name, rl)
+        assert st["nonphysical"] == 0 and st["steps"] == 200, (k, st)
+        e = {q: "%.1e/%.1e" % v[:2] for q, v in
+             field_errors(s.get_state_cons(), U200[k], names).items()}
+        announce("  200 steps (reported) member %d n=%s: %s" % (k, probs[k].n[:2], e))
     b.close()
+
+    announce("full batch fp32, step 200 from the oracle's state after 199 steps")
+    sv2 = []
+    for k, p in enumerate(probs):
+        s = rbdi.Solver(p, "fp32")
+        s.set_state_cons(U199[k])
+        sv2.append(s)
+    b2 = rbdi.Batch(sv2)
+    b2.autotune(reps=2)
+    b2.step([d[199] for d in dts], probs[0].cfl)
+    compare(sv2, U200, "step 200")
+    b2.close()
 
 
 def _sphere_3d(n, amp):
@@ -223,4 +258,4 @@ def test_batch_3d_equals_single_and_oracle(rbdi):
         assert np.array_equal(s.get_state_cons(), bat[k])
         o = oracle.Oracle(p)
         o.run(dts=dts[k])
-        assert np.all(rel_l1(bat[k], o.get_state_cons()) <= TOL64)
+        check_fields(bat[k], o.get_state_cons(), p.cons_names(), "fp64", p.name)

@@ -7,7 +7,8 @@ Bars: features/targets to FP32 rounding; forward pass equal to the oracle
 with the same BF16 rounding of weights and layer inputs up to FP32
 accumulation order; gradients: cosine >= 0.999 and relative L2 <= 2e-2 per
 tensor against the FP64 backward pass; the solver with the surrogate within
-1e-4 relative L1 per conserved field of the FP64 oracle (exact closure).
+the FP32 bars (relative L1 1e-4, Linf 1e-3 per conserved field) of the FP64
+oracle (exact closure).
 """
 import time
 
@@ -17,7 +18,7 @@ import pytest
 import oracle
 from oracle import mlp as omlp
 from paper_2111_11806_amd import inputs
-from parity_util import announce, rel_l1, rel_l1_grouped
+from parity_util import FP32_SOLID_CONTACT, FP32_SOLID_MOMENTUM, announce, check_fields, non_rigid
 
 pytestmark = pytest.mark.gpu
 
@@ -144,8 +145,8 @@ def test_surrogate_strain_accuracy_and_gain(rbdi, trained):
     assert np.median(e_net) <= np.median(e_base)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-4), ("fp32", 1e-4)])
-def test_solver_with_surrogate_vs_oracle(rbdi, trained, precision, tol):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solver_with_surrogate_vs_oracle(rbdi, trained, precision):
     net, _, _ = trained
     prob = inputs.copper_indenter(24)
     orc = oracle.Oracle(prob)
@@ -156,17 +157,9 @@ def test_solver_with_surrogate_vs_oracle(rbdi, trained, precision, tol):
     st = s.status()
     announce(f"surrogate {precision}: net {st['surr_net']} exact {st['surr_exact']}")
     assert st["nonphysical"] == 0 and st["surr_net"] > 0
-    U, U0 = s.get_state_cons(), orc.get_state_cons()
-    rl = rel_l1(U, U0)
-    rg = rel_l1_grouped(U, U0, prob)
-    announce("  rel L1 per component " + np.array2string(rl, precision=2))
-    announce("  rel L1 per quantity " + ", ".join("%s %.2e" % kv for kv in rg.items()))
-    if precision == "fp64":
-        assert np.all(rl <= tol), rl
-    else:
-        # FP32 storage: components that nearly vanish (shear stretches,
-        # transverse momenta) carry FP32 rounding of their O(1) neighbours
-        assert max(rg.values()) <= tol, rg
+    # the surrogate approximates the closure: the FP32 bars in either precision
+    check_fields(s.get_state_cons(), orc.get_state_cons(), prob.cons_names(), "fp32",
+                 f"surrogate {precision}", field_bars=FP32_SOLID_MOMENTUM if precision == "fp32" else None)
 
 
 def test_surrogate_advance_and_gain_timing(rbdi, trained):
@@ -188,15 +181,14 @@ def test_surrogate_advance_and_gain_timing(rbdi, trained):
         torch.cuda.synchronize()
         res[mode] = ((time.perf_counter() - t0) / 10, s.get_state_cons(), s.status())
     announce("ms/step exact %.3f surrogate %.3f" % (res["exact"][0] * 1e3, res["surrogate"][0] * 1e3))
-    rl = rel_l1(res["surrogate"][1], res["exact"][1])
-    assert np.all(rl <= 1e-4), rl
+    check_fields(res["surrogate"][1], res["exact"][1], prob.cons_names(), "fp32", "surrogate vs exact")
     assert res["surrogate"][2]["steps"] == res["exact"][2]["steps"] == 13
 
 
-def test_autotune_with_the_surrogate_pass(rbdi, trained):
-    """The surrogate pass swaps the state buffers every step; rbdi_autotune
-    puts the buffer order back with the state, so the tuned solver continues
-    bitwise like an untuned one (FP32 copper 24^3 with the network)."""
+def test_autotune_with_the_surrogate(rbdi, trained):
+    """rbdi_autotune with the surrogate's x sweep: it puts the state back,
+    so the tuned solver continues bitwise like an untuned one (FP32 copper
+    24^3 with the network)."""
     net, _, _ = trained
     prob = inputs.copper_indenter(24)
     a = rbdi.Solver(prob, "fp32")
@@ -215,3 +207,53 @@ def test_autotune_with_the_surrogate_pass(rbdi, trained):
     b.advance(prob.cfl, 4)
     assert np.array_equal(a.get_state_cons(), b.get_state_cons())
     assert a.status()["surr_net"] == b.status()["surr_net"]
+
+
+def test_surrogate_gain_at_full_size_in_contact(rbdi, trained):
+    """What the layers on the plain FP64 solver gain on the 256^3 copper
+    indenter under load (the flat end starts two cells inside the copper, so
+    the plastic return runs from the first step): time per step of FP64
+    exact, FP32 exact and FP32 with the surrogate closure, measured on the
+    same GPU over the same steps. Asserted: FP32 + surrogate is faster than
+    FP64 exact, within the bars of the FP32 storage floor through contact of
+    it (non-rigid cells) and within the FP32 bars of FP32 with the exact
+    closure; the network, which runs inside the final sweep (no pass of its
+    own), costs at most 15% over FP32 with the exact closure. Reported: all
+    three times and the split of plastic returns between network and exact
+    closure."""
+    import torch
+    net, _, _ = trained
+    prob = inputs.copper_indenter(256, gap=-2 * 25.6e-3 / 256)
+    stream = torch.cuda.current_stream()
+    nsteps = 5
+    res = {}
+    for mode, prec, surr in (("fp64_exact", "fp64", False), ("fp32_exact", "fp32", False),
+                             ("fp32_surrogate", "fp32", True)):
+        s = rbdi.Solver(prob, prec, stream=stream)
+        if surr:
+            s.set_surrogate(net)
+        s.advance(prob.cfl, 1, prob.t_end)  # warm-up step (not timed)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.advance(prob.cfl, nsteps, prob.t_end)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = s.status()
+        res[mode] = (e0.elapsed_time(e1) / nsteps, s.get_state_cons(), st)
+        s.close()
+    t64, t32, tsu = (res[m][0] for m in ("fp64_exact", "fp32_exact", "fp32_surrogate"))
+    st = res["fp32_surrogate"][2]
+    announce("256^3 in contact, ms/step: fp64 exact %.2f, fp32 exact %.2f, fp32 + surrogate %.2f "
+             "(speedup over fp64 %.2fx; surrogate / fp32 exact %.3f); plastic returns by the network %d, "
+             "by the exact closure %d" % (t64, t32, tsu, t64 / tsu, tsu / t32, st["surr_net"], st["surr_exact"]))
+    assert st["nonphysical"] == 0 and st["surr_net"] > 0
+    assert res["fp32_surrogate"][2]["steps"] == res["fp64_exact"][2]["steps"] == nsteps + 1
+    names = prob.cons_names()
+    a, b = non_rigid(res["fp32_surrogate"][1], res["fp64_exact"][1], names)
+    check_fields(a, b, names, "fp32", "fp32 + surrogate vs fp64 exact (non-rigid cells)",
+                 field_bars=FP32_SOLID_CONTACT)
+    check_fields(res["fp32_surrogate"][1], res["fp32_exact"][1], names, "fp32", "fp32 + surrogate vs fp32 exact")
+    assert tsu < t64
+    assert tsu <= 1.15 * t32
