@@ -196,14 +196,18 @@ struct Impl {
       launch(h, 3, k_seed<S, T, false>, dim3(256), dim3(256), 0, h->P, u(h, 0), (const SeedTask*)h->tasks,
              h->task_cap, h->sc, A);
   }
-  // Wavefronts per x-sweep block: 1 in 1D; in 2D, 4 or 2, whichever leaves
-  // fewer idle wavefronts at the end of a row (4 on ties; measured on the
-  // 1024-cell rows of the shock/cylinder grid: 18 segments run 1.4% faster
-  // per step as 9 blocks of 2 than as 5 blocks of 4); 4 in 3D.
+  // Wavefronts per x-sweep block: 1 in 1D and for the elastoplastic systems
+  // (their blocks hold LDS per wavefront and nothing per block, so a block of
+  // one leaves no wavefront idle: on the 256-cell rows of the 256^3 copper
+  // grid, 5 segments, an FP64 x sweep takes 4.8 ms as 5 blocks of 1, 5.1 ms
+  // as 3 blocks of 2, 7.6 ms as 2 blocks of 4); otherwise 4 or 2, whichever
+  // leaves fewer idle wavefronts at the end of a row (4 on ties; measured on
+  // the 1024-cell rows of the shock/cylinder grid: 18 segments run 1.4%
+  // faster per step as 9 blocks of 2 than as 5 blocks of 4).
   static int x_wpb(const rbdi_handle* h) {
     if (S::D == 1) return 1;
     if (h->x_waves > 0) return h->x_waves;  // rbdi_set_x_waves / rbdi_autotune
-    if (S::D == 3) return kWPB;
+    if (S::S) return 1;
     const int nseg = (h->P.n[0] + kOut - 1) / kOut;
     const int idle4 = (nseg + 3) / 4 * 4 - nseg, idle2 = (nseg + 1) / 2 * 2 - nseg;
     return idle2 < idle4 ? 2 : 4;
@@ -218,12 +222,14 @@ struct Impl {
   static void sweep_x_mb(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
     if constexpr (S::S) {
       if (h->P.surr) {  // the surrogate sources inside the final sweep
-        launch(h, 0, k_sweep_x_surr<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0,
+        launch(h, 0, k_sweep_x_surr<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)),
+               (unsigned)(x_wpb(h) * sizeof(XSurrLds<S, T>)), h->P, Uin, U0,
                (const T*)h->D, Uout, h->sc, h->cflpart, A, b, stage, mlp_dev(h->mlp));
         return;
       }
     }
-    launch(h, 0, k_sweep_x<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), 0, h->P, Uin, U0, (const T*)h->D, Uout,
+    launch(h, 0, k_sweep_x<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), x_sweep_lds<S, T>(x_wpb(h)), h->P, Uin,
+           U0, (const T*)h->D, Uout,
            h->sc, h->cflpart, A, b, stage);
   }
   static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {

@@ -577,6 +577,37 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
 // not force spills (measured on the 2D x sweep: four, 128 registers without
 // spills, beats five with spills and six; the LDS tile holds the y/z sweeps
 // at three). Other systems: the compiler's choice (1 = no request).
+// XCD-aware block order: workgroups are dispatched round-robin over the 8
+// XCDs by flat id, and each XCD has its own L2. The blocks that one XCD runs
+// (flat ids = its index mod 8) take a contiguous run of the grid's blocks in
+// x-fastest order instead of every eighth one, so neighbouring blocks whose
+// loads share cache lines (tile rows of TC values, 32-128 bytes; x-sweep
+// segments overlapping by their halos) run on the same L2 at about the same
+// time. Returns the block's logical linear index.
+__device__ inline int xcd_block(int& bx, int& by, int& bz) {
+  const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+  const int n = gx * gy * (int)gridDim.z;
+  const int b = (int)blockIdx.x + gx * ((int)blockIdx.y + gy * (int)blockIdx.z);
+  const int xcd = b & 7, q = n >> 3, r = n & 7;
+  const int l = xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+  bx = l % gx;
+  by = (l / gx) % gy;
+  bz = l / (gx * gy);
+  return l;
+}
+
+// Dynamic LDS of a launch (bytes given at the launch), as an array of T.
+template <typename T>
+__device__ inline T* dyn_lds() {
+  extern __shared__ __align__(16) unsigned char rbdi_dyn_lds[];
+  return reinterpret_cast<T*>(rbdi_dyn_lds);
+}
+
+// LDS bytes of an x-sweep block of wpb wavefronts: the elastoplastic sweeps
+// stage each wavefront's streamed d (nfields x 64 values).
+template <class S, typename T>
+constexpr unsigned x_sweep_lds(int wpb) { return S::S ? (unsigned)(wpb * S::NF * kWave * sizeof(T)) : 0u; }
+
 template <class S>
 constexpr int x_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 4; }
 template <class S>
@@ -588,16 +619,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                                 StepArgs A, double bcoef, int stage) {
   const int wpb = blockDim.x / kWave;
-  const long long blin = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  int bx, by, bz;
+  const long long blin = xcd_block(bx, by, bz);
   const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
   if constexpr (S::S) {
-    __shared__ T xlds[kMaxWPB * S::NF * kWave];
-    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x,
-                                         blockIdx.y, blockIdx.z, blin, wpb, nparts,
-                                         xlds + (threadIdx.x / kWave) * S::NF * kWave);
+    // per-wavefront staging of the streamed d, sized by the launch for the
+    // block's wavefronts (a static size for the largest block would hold
+    // LDS that 1- and 2-wavefront blocks never use and cap their occupancy)
+    T* xlds = dyn_lds<T>();
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
+                                         wpb, nparts, xlds + (threadIdx.x / kWave) * S::NF * kWave);
   } else {
-    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, blockIdx.x,
-                                         blockIdx.y, blockIdx.z, blin, wpb, nparts);
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
+                                         wpb, nparts);
   }
 }
 
@@ -735,14 +769,16 @@ __device__ __forceinline__ void sweep_tile_body(const Params& P, const T* __rest
   }
 }
 
+
 template <class S, typename T, int DIR, int MODE, bool REDUCE, bool MB = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(tile_sweep_waves<S>()))) void k_sweep_tile(Params P, const T* __restrict__ Uin, T* __restrict__ Dacc,
                                                    DevScalars* __restrict__ sc, const double* __restrict__ cflpart,
                                                    StepArgs A) {
   constexpr int TC = tile_cols<S, T>();
   __shared__ T tile[S::NF * TC * kRS];
-  sweep_tile_body<S, T, DIR, MODE, REDUCE, MB>(P, Uin, Dacc, sc, cflpart, A, blockIdx.x, blockIdx.y, blockIdx.z,
-                                               tile, TC);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  sweep_tile_body<S, T, DIR, MODE, REDUCE, MB>(P, Uin, Dacc, sc, cflpart, A, bx, by, bz, tile, TC);
 }
 
 // ---------------------------------------------------------------------------

@@ -262,6 +262,14 @@ class Solver:
         _check(load().rbdi_get_state_cons(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
 
+    def get_state_cons_device(self, ptr):
+        """Conserved state into FP64 device memory at ptr (shape self.shape)."""
+        _check(load().rbdi_get_state_cons(self._h, ctypes.c_void_p(int(ptr)), 1))
+
+    def set_state_cons_device(self, ptr):
+        """Conserved state from FP64 device memory at ptr (shape self.shape)."""
+        _check(load().rbdi_set_state_cons(self._h, ctypes.c_void_p(int(ptr)), 1))
+
     def set_rigid_sdf(self, sdf, width, v, omega, center):
         a = _arr(sdf, int(np.prod(self.shape[1:])))
         _check(load().rbdi_set_rigid_sdf(self._h, a.ctypes.data_as(ctypes.c_void_p), 0, float(width),
