@@ -37,7 +37,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_cylinder_1024x512_fp64.txt")
+TRAFFIC_CYLINDER = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_cylinder_1024x512_fp64.txt")
+TRAFFIC_COPPER = os.path.join(ROOT, "profiles", "traffic_sweeps_copper_indenter_256_fp64.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_11806_amd", "csrc", f)
                   for f in ("rbdi_api.hip", "rbdi_batch.hpp", "rbdi_kernels.hpp", "rbdi_mlp.hpp", "rbdi_physics.hpp")]
 
@@ -51,15 +52,16 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(ncell):
-    """HBM bytes of one RK stage (y sweep + x sweep, averages per launch) from
-    the rocprofv3 FETCH_SIZE / WRITE_SIZE summary, each counter scaled by what
-    it reads for a device copy of known size; None when the summary is
-    missing or was taken on other kernel sources, or on another grid."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+def measured_traffic(path, ncell, sweeps):
+    """HBM bytes of one RK stage (the named sweeps, averages per launch) from
+    a rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, each counter
+    scaled by what it reads for a device copy of known size; None when the
+    summary is missing or was taken on other kernel sources, or on another
+    grid."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_PROFILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -67,12 +69,11 @@ def measured_traffic(ncell):
     try:
         if kv.get("source_sha1") != kernel_source_hash() or int(kv["cells"]) != ncell:
             return None
-        cb = float(kv["copy_bytes_read"])
-        f_scale = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+        f_scale = float(kv["copy_bytes_read"]) / (float(kv["copy_fetch_kib"]) * 1024.0)
         w_scale = float(kv["copy_bytes_written"]) / (float(kv["copy_write_kib"]) * 1024.0)
-        fetch = (float(kv["sweep_y_fetch_kib"]) + float(kv["sweep_x_fetch_kib"])) * 1024.0 * f_scale
-        write = (float(kv["sweep_y_write_kib"]) + float(kv["sweep_x_write_kib"])) * 1024.0 * w_scale
-        return fetch + write
+        fetch = sum(float(kv[f"{k}_fetch_kib"]) for k in sweeps) * 1024.0 * f_scale
+        write = sum(float(kv[f"{k}_write_kib"]) for k in sweeps) * 1024.0 * w_scale
+        return round(fetch + write)
     except (KeyError, ValueError, ZeroDivisionError):
         return None
 
@@ -182,15 +183,26 @@ def run_batched(steps, warmup, precision="fp32"):
 COPPER_PREROLL_T = 0.6e-6  # past the contact at 0.5 us
 
 
-def stage_roofline(ms_stage_us, bytes_per_cell_step, ncell, kernel, avg_us, traffic=None):
+def stage_roofline(ms_stage_us, bytes_per_cell_step, ncell, kernel, avg_us, traffic=None, design_bytes=None):
     """HBM roofline of one RK stage: algorithmic bytes (one third of the
-    per-step bytes) over the summed durations of the stage's sweeps."""
+    per-step bytes) over the summed durations of the stage's sweeps.
+    design_bytes: what the direction-split sweeps move by design (each sweep
+    reads the stage input, the y/x sweeps read the accumulator D the earlier
+    ones wrote, the x sweep U^n), the measured traffic's reference."""
     achieved = (bytes_per_cell_step / 3.0) * ncell / (ms_stage_us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_stage": round(bytes_per_cell_step / 3.0 * ncell),
+            "design_bytes_per_stage": design_bytes,
             "bytes_per_cell_step": bytes_per_cell_step, "kernel": kernel,
             "avg_us": {k: round(v, 2) for k, v in avg_us.items()}}
+
+
+def design_bytes_per_stage(dim, nfields, elem, ncell):
+    """Plane accesses per field and stage of the direction-split sweeps: 3D
+    z (read U, write D), y (read U, D; write D), x (read U, U^n, D; write
+    U): 9; 2D y + x: 6."""
+    return (9 if dim == 3 else 6) * nfields * elem * ncell
 
 
 def copper_leg(prob, precision, net, steps, warmup, stream):
@@ -432,9 +444,9 @@ def run_shock_cylinder(nx, ny, steps, warmup):
     s64, ms64, wall64, st64, kt64 = run_gpu(prob, "fp64", steps, warmup, cfl, timing_steps)
     B64 = algorithmic_bytes_per_cell_step(4, 1, 8)
     rx, ry = kt64["replay_us"]["sweep_x"], kt64["replay_us"]["sweep_y"]
-    traffic = measured_traffic(ncell)
+    traffic = measured_traffic(TRAFFIC_CYLINDER, ncell, ("sweep_y", "sweep_x"))
     roof = stage_roofline(rx + ry, B64, ncell, "one RK stage: k_sweep_tile<y> + k_sweep_x (fp64)",
-                          {"sweep_x": rx, "sweep_y": ry}, None if traffic is None else round(traffic))
+                          {"sweep_x": rx, "sweep_y": ry}, traffic, design_bytes_per_stage(2, 5, 8, ncell))
     out = {"workload": "shock_cylinder", "nx": nx, "ny": ny, "cells": ncell, "dtype": "f64", "steps": steps,
            "warmup": warmup, "ms_per_step": ms64 / steps, "value": ncell * steps / (ms64 * 1e-3),
            "unit": "cell-updates/s", "t_start_timed": st64["t_start"], "t_reached": st64["t"],
@@ -513,9 +525,12 @@ def main():
 
     def leg_roof(L, B, dtype):
         r = L["replay_us"]
+        traffic = (measured_traffic(TRAFFIC_COPPER, ncell, ("sweep_z", "sweep_y", "sweep_x"))
+                   if dtype == "f64" else None)
         return stage_roofline(r["sweep_x"] + r["sweep_y"] + r["sweep_z"], B, ncell,
                               "one RK stage: k_sweep_tile<z> + k_sweep_tile<y> + k_sweep_x%s (%s)"
-                              % ("_surr" if dtype == "f32+surrogate" else "", dtype), r)
+                              % ("_surr" if dtype == "f32+surrogate" else "", dtype), r, traffic,
+                              design_bytes_per_stage(3, prob.nfields, 8 if dtype == "f64" else 4, ncell))
 
     def worst_l1(part):
         return max(part.values(), key=lambda v: v["l1"])["l1"]
