@@ -484,7 +484,8 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=100,
                     help="steps of the FP32 + surrogate vs FP64 comparison after contact (0: skip)")
     ap.add_argument("--copper-legs", default=",".join(COPPER_LEGS),
-                    help="comma list of copper legs to run (profiling); the JSON line needs all three")
+                    help="comma list of copper legs to run, or none (profiling runs); the JSON line "
+                         "needs all three")
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--cyl-steps", type=int, default=1000)
@@ -509,14 +510,23 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    wanted = tuple(x for x in args.copper_legs.split(",") if x)
-    prob, legs, acc, training = run_copper(args.copper_n, args.steps, args.warmup, args.accuracy_steps, wanted)
+    wanted = tuple(x for x in args.copper_legs.split(",") if x and x != "none")
     if set(wanted) != set(COPPER_LEGS):
-        # a profiling run: timings of the legs it ran and the device copy that
-        # scales the traffic counters, no JSON line
-        print(json.dumps({"legs": {k: {"ms_per_step": v["ms_per_step"], "replay_us": v["replay_us"]}
-                                   for k, v in legs.items()}, "hbm_copy": hbm_copy()}))
+        # a profiling run: the legs it names (none, or some copper legs, and
+        # the shock/cylinder workload unless --no-cylinder), their timings and
+        # the device copy that scales the traffic counters; no headline line
+        out = {}
+        if wanted:
+            _, legs, _, _ = run_copper(args.copper_n, args.steps, args.warmup, 0, wanted)
+            out["legs"] = {k: {"ms_per_step": v["ms_per_step"], "replay_us": v["replay_us"]}
+                           for k, v in legs.items()}
+        if not args.no_cylinder:
+            c = run_shock_cylinder(args.nx, args.ny, args.cyl_steps, args.cyl_warmup)
+            out["shock_cylinder"] = {"ms_per_step": c["ms_per_step"], "avg_us": c["roofline"]["avg_us"]}
+        out["hbm_copy"] = hbm_copy()
+        print(json.dumps(out))
         return
+    prob, legs, acc, training = run_copper(args.copper_n, args.steps, args.warmup, args.accuracy_steps, wanted)
     ncell = prob.ncells
     L64, Ls, L32 = legs["fp64_exact"], legs["fp32_surrogate"], legs["fp32_exact"]
     n_dyn = prob.nfields  # every field of the elastoplastic system is dynamic (r moves with the body)

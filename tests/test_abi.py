@@ -98,21 +98,22 @@ def test_empty_and_oversized_grids_are_rejected():
     assert lib.rbdi_create(ctypes.byref(d), ctypes.byref(h)) == -1
 
 
-def test_bench_traffic_needs_matching_sources(tmp_path, monkeypatch):
+def test_bench_traffic_needs_matching_sources(tmp_path):
     """The benchmark reports measured HBM traffic only from a counter summary
     taken on the current kernel sources and grid."""
     import bench
-    good = bench.measured_traffic(524288)
+    sweeps = ("sweep_z", "sweep_y", "sweep_x")
+    good = bench.measured_traffic(bench.TRAFFIC_COPPER, 256 ** 3, sweeps)
     if good is not None:
-        assert bench.measured_traffic(524288 * 2) is None
+        assert bench.measured_traffic(bench.TRAFFIC_COPPER, 128 ** 3, sweeps) is None
     fake = tmp_path / "traffic.txt"
-    good_keys = ["source_sha1: 0000", "cells: 524288", "copy_bytes_read: 1", "copy_bytes_written: 1",
-                 "copy_fetch_kib: 1", "copy_write_kib: 1", "sweep_y_fetch_kib: 1", "sweep_y_write_kib: 1",
-                 "sweep_x_fetch_kib: 1", "sweep_x_write_kib: 1"]
-    fake.write_text("\n".join(good_keys) + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake))
-    assert bench.measured_traffic(524288) is None          # other sources
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000")
+    keys = ["cells: 524288", "copy_bytes_read: 1", "copy_bytes_written: 1", "copy_fetch_kib: 1",
+            "copy_write_kib: 1", "sweep_y_fetch_kib: 1", "sweep_y_write_kib: 1", "sweep_x_fetch_kib: 1",
+            "sweep_x_write_kib: 1"]
+    fake.write_text("\n".join(["source_sha1: 0000"] + keys) + "\n")
+    assert bench.measured_traffic(str(fake), 524288, ("sweep_y", "sweep_x")) is None  # other sources
+    fake.write_text("\n".join(["source_sha1: " + bench.kernel_source_hash()] + keys) + "\n")
     # 2 + 2 KiB counted, each KiB worth 1 byte by the copy scale: 4 bytes
-    assert bench.measured_traffic(524288) == 4.0
-    assert bench.measured_traffic(1000) is None            # other grid
+    assert bench.measured_traffic(str(fake), 524288, ("sweep_y", "sweep_x")) == 4
+    assert bench.measured_traffic(str(fake), 1000, ("sweep_y", "sweep_x")) is None    # other grid
+    assert bench.measured_traffic(str(fake), 524288, sweeps) is None                  # a sweep missing
