@@ -45,6 +45,7 @@ struct rbdi_handle {
   int elem = 8;            // bytes per stored value
   void* U[3] = {nullptr, nullptr, nullptr};
   void* D = nullptr;
+  void* D2 = nullptr;  // 3D: the y sweep's part of the operator (the z sweep's is in D)
   double* stage_buf = nullptr;  // FP64 staging for API transfers (nf * ncell)
   SeedTask* tasks = nullptr;    // seeding tasks of the rigid band
   int task_cap = 0;
@@ -224,20 +225,21 @@ struct Impl {
       if (h->P.surr) {  // the surrogate sources inside the final sweep
         launch(h, 0, k_sweep_x_surr<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)),
                (unsigned)(x_wpb(h) * sizeof(XSurrLds<S, T>)), h->P, Uin, U0,
-               (const T*)h->D, Uout, h->sc, h->cflpart, A, b, stage, mlp_dev(h->mlp));
+               (const T*)h->D, (const T*)h->D2, Uout, h->sc, h->cflpart, A, b, stage, mlp_dev(h->mlp));
         return;
       }
     }
     launch(h, 0, k_sweep_x<S, T, MB>, x_grid(h), dim3(kWave * x_wpb(h)), x_sweep_lds<S, T>(x_wpb(h)), h->P, Uin,
-           U0, (const T*)h->D, Uout,
+           U0, (const T*)h->D, (const T*)h->D2, Uout,
            h->sc, h->cflpart, A, b, stage);
   }
   static void sweep_x(rbdi_handle* h, const T* Uin, const T* U0, T* Uout, const StepArgs& A, double b, int stage) {
     if (multi(h)) sweep_x_mb<true>(h, Uin, U0, Uout, A, b, stage);
     else sweep_x_mb<false>(h, Uin, U0, Uout, A, b, stage);
   }
+  // dst: the accumulator (D, or in 3D D2 for the y sweep)
   template <int DIR, int MODE, bool REDUCE>
-  static void sweep_t(rbdi_handle* h, const T* Uin, const StepArgs& A) {
+  static void sweep_t(rbdi_handle* h, const T* Uin, const StepArgs& A, void* dst) {
     const Params& P = h->P;
     constexpr int TC = tile_cols<S, T>();
     const unsigned nseg = (unsigned)((P.n[DIR] + kOut - 1) / kOut);
@@ -245,10 +247,10 @@ struct Impl {
     const dim3 grid = DIR == 1 ? dim3(gx, nseg, (unsigned)P.n[2]) : dim3(gx, (unsigned)P.n[1], nseg);
     if (multi(h))
       launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE, true>, grid, dim3(kTileThreads), 0, P, Uin,
-             static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
+             static_cast<T*>(dst), h->sc, (const double*)h->cflpart, A);
     else
       launch(h, DIR, k_sweep_tile<S, T, DIR, MODE, REDUCE, false>, grid, dim3(kTileThreads), 0, P, Uin,
-             static_cast<T*>(h->D), h->sc, (const double*)h->cflpart, A);
+             static_cast<T*>(dst), h->sc, (const double*)h->cflpart, A);
   }
   static void stages(rbdi_handle* h, const StepArgs& A) {
     const double bc[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -259,12 +261,12 @@ struct Impl {
       const T* U0 = u(h, 0);
       T* Uout = u(h, out_[s]);
       if constexpr (S::D == 3) {
-        if (s == 0) sweep_t<2, 0, true>(h, Uin, A);
-        else sweep_t<2, 0, false>(h, Uin, A);
-        sweep_t<1, 1, false>(h, Uin, A);
+        if (s == 0) sweep_t<2, 0, true>(h, Uin, A, h->D);
+        else sweep_t<2, 0, false>(h, Uin, A, h->D);
+        sweep_t<1, 0, false>(h, Uin, A, h->D2);
       } else if constexpr (S::D == 2) {
-        if (s == 0) sweep_t<1, 0, true>(h, Uin, A);
-        else sweep_t<1, 0, false>(h, Uin, A);
+        if (s == 0) sweep_t<1, 0, true>(h, Uin, A, h->D);
+        else sweep_t<1, 0, false>(h, Uin, A, h->D);
       }
       sweep_x(h, Uin, U0, Uout, A, bc[s], s);
     }
@@ -303,10 +305,10 @@ struct Impl {
     A.rhs_only = 1 | ((~dirmask & 7) << 1);
     const T* U0 = u(h, 0);
     if constexpr (S::D == 3) {
-      sweep_t<2, 0, false>(h, U0, A);
-      sweep_t<1, 1, false>(h, U0, A);
+      sweep_t<2, 0, false>(h, U0, A, h->D);
+      sweep_t<1, 0, false>(h, U0, A, h->D2);
     } else if constexpr (S::D == 2) {
-      sweep_t<1, 0, false>(h, U0, A);
+      sweep_t<1, 0, false>(h, U0, A, h->D);
     }
     sweep_x(h, U0, U0, u(h, 1), A, 1.0, 0);
   }
@@ -319,12 +321,9 @@ struct Impl {
     const T* U1 = u(h, 1);
     if (cls == 0) sweep_x(h, U1, u(h, 0), u(h, 2), A, 0.25, 1);
     if constexpr (S::D >= 2)
-      if (cls == 1) {
-        if constexpr (S::D == 3) sweep_t<1, 1, false>(h, U1, A);
-        else sweep_t<1, 0, false>(h, U1, A);
-      }
+      if (cls == 1) sweep_t<1, 0, false>(h, U1, A, S::D == 3 ? h->D2 : h->D);
     if constexpr (S::D == 3)
-      if (cls == 2) sweep_t<2, 0, false>(h, U1, A);
+      if (cls == 2) sweep_t<2, 0, false>(h, U1, A, h->D);
   }
   // what: 0 face flux (dir), 1 closure, 2 solid sources
   static void unit(rbdi_handle* h, int what, int dir, const double* a, const double* b, double* out, int n) {
@@ -374,11 +373,11 @@ void free_all(rbdi_handle* h) {
   h->ev.clear();
   for (auto& p : h->U)
     if (p) { (void)hipFree(p); p = nullptr; }
-  void* ptrs[] = {h->D, h->stage_buf, h->tasks, h->sc, h->part, h->red_out, h->cflpart};
+  void* ptrs[] = {h->D, h->D2, h->stage_buf, h->tasks, h->sc, h->part, h->red_out, h->cflpart};
   h->mlp = nullptr;
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  h->D = nullptr; h->stage_buf = nullptr; h->tasks = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
+  h->D = nullptr; h->D2 = nullptr; h->stage_buf = nullptr; h->tasks = nullptr; h->sc = nullptr; h->part = nullptr; h->red_out = nullptr;
   h->cflpart = nullptr;
 }
 
@@ -475,6 +474,7 @@ RBDI_API int rbdi_create(const rbdi_desc* d, rbdi_handle** out) {
   hipError_t e = hipSuccess;
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMalloc(&h->U[k], state_bytes);
   if (e == hipSuccess) e = hipMalloc(&h->D, state_bytes);
+  if (e == hipSuccess && d->dim == 3) e = hipMalloc(&h->D2, state_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&h->stage_buf, (size_t)ncell * h->nf * sizeof(double));
   h->task_cap = (int)std::max<long long>(4096, ncell / 4);
   if (e == hipSuccess) e = hipMalloc((void**)&h->tasks, (size_t)h->task_cap * sizeof(SeedTask));

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void kb_sweep_x(const BatchInst<T>* __restrict
     const StepArgs A = batch_step_args(bi, B, it.inst);
     const int nseg = (bi.P.n[0] + kOut - 1) / kOut;
     const int nparts = (nseg + wpb - 1) / wpb * wpb * bi.P.n[1] * bi.P.n[2];
-    sweep_x_body<S, T>(bi.P, bi.U[B.in], bi.U[0], bi.D, bi.U[B.out], bi.sc, bi.cflpart, A, B.bcoef, B.stage,
+    sweep_x_body<S, T>(bi.P, bi.U[B.in], bi.U[0], bi.D, nullptr, bi.U[B.out], bi.sc, bi.cflpart, A, B.bcoef, B.stage,
                        it.bx, it.by, it.bz, it.blin, wpb, nparts);
   }
 }

@@ -455,7 +455,8 @@ struct ExactSources {
 // may work across the wavefront (the surrogate's matrix instructions).
 template <class S, typename T, class Src = ExactSources, bool MB = false>
 __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restrict__ Uin, const T* __restrict__ U0,
-                                             const T* __restrict__ Dacc, T* __restrict__ Uout,
+                                             const T* __restrict__ Dacc, const T* __restrict__ Dacc2,
+                                             T* __restrict__ Uout,
                                              DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                              const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
                                              long long blin, int wpb, int nparts, T* xw = nullptr,
@@ -508,11 +509,22 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   if (outlane && S::D > 1) {
     // with a static body r's operator is zero and the y/z sweeps do not
     // store its row of D: the loaded value is discarded by a select (a
-    // branch around the loads measured slower than the bytes it saves)
+    // branch around the loads measured slower than the bytes it saves).
+    // In 3D the z and y sweeps leave their parts in D and D2 (a y sweep
+    // that added into D read it back first); both are added here in the
+    // order d_z + d_y + d_x.
+    if (S::D == 3 && Dacc2) {
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) {
-      const T dq = Dacc[q * P.fs + c];
-      d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
+      for (int q = 0; q < S::NF; ++q) {
+        const T dq = Dacc[q * P.fs + c] + Dacc2[q * P.fs + c];
+        d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) {
+        const T dq = Dacc[q * P.fs + c];
+        d[q] = (q == S::R && P.r_static) ? d[q] : dq + d[q];
+      }
     }
   }
   if (A.rhs_only) {  // uniform over the grid
@@ -615,7 +627,8 @@ constexpr int tile_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 3; }
 
 template <class S, typename T, bool MB = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x(Params P, const T* __restrict__ Uin, const T* __restrict__ U0,
-                                                const T* __restrict__ Dacc, T* __restrict__ Uout,
+                                                const T* __restrict__ Dacc, const T* __restrict__ Dacc2,
+                                                T* __restrict__ Uout,
                                                 DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                                 StepArgs A, double bcoef, int stage) {
   const int wpb = blockDim.x / kWave;
@@ -627,10 +640,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
     // block's wavefronts (a static size for the largest block would hold
     // LDS that 1- and 2-wavefront blocks never use and cap their occupancy)
     T* xlds = dyn_lds<T>();
-    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
                                          wpb, nparts, xlds + (threadIdx.x / kWave) * S::NF * kWave);
   } else {
-    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
+    sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
                                          wpb, nparts);
   }
 }

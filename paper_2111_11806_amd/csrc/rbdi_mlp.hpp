@@ -646,7 +646,8 @@ union XSurrLds {
 
 template <class S, typename T, bool MB = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_waves<S>()))) void k_sweep_x_surr(
-    Params P, const T* __restrict__ Uin, const T* __restrict__ U0, const T* __restrict__ Dacc, T* __restrict__ Uout,
+    Params P, const T* __restrict__ Uin, const T* __restrict__ U0, const T* __restrict__ Dacc,
+    const T* __restrict__ Dacc2, T* __restrict__ Uout,
     DevScalars* __restrict__ sc, double* __restrict__ cflpart, StepArgs A, double bcoef, int stage, MlpDev m) {
   XSurrLds<S, T>* lds = dyn_lds<XSurrLds<S, T>>();  // one per wavefront, sized by the launch
   const int wpb = blockDim.x / kWave;
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
   const int nparts = (int)(gridDim.x * gridDim.y * gridDim.z) * wpb;
   XSurrLds<S, T>* my = &lds[threadIdx.x / kWave];
   SurrogateSources src{m, &my->mlp, sc};
-  sweep_x_body<S, T, SurrogateSources, MB>(P, Uin, U0, Dacc, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
+  sweep_x_body<S, T, SurrogateSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
                                            wpb, nparts, my->d, src);
 }
 
