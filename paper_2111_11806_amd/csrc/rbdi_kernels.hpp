@@ -459,7 +459,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
                                              T* __restrict__ Uout,
                                              DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                              const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
-                                             long long blin, int wpb, int nparts, T* xw = nullptr,
+                                             long long blin, int wpb, int nparts, T* xw = nullptr, T* xu = nullptr,
                                              const Src& src = Src()) {
   const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
@@ -485,6 +485,12 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     const int mode = ghost_map(P, 0, posl, src, face);
     if (mode != 2) {
       load_cons<S>(P, Uin, cell_index(P, src, j, k), Uc);
+      if constexpr (S::S) {
+        // kept for the combine in this lane's own LDS slots (read back by
+        // the same lane: no barrier) rather than in registers or reloaded
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q) xu[q * kWave + lane] = Uc[q];
+      }
       cons_to_prim<S>(P, Uc, W);
     }
     ghost_fix<S, T, 0>(P, mode, face, W);
@@ -492,7 +498,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   T d[S::NF];
   if constexpr (S::S) {
     // streamed: this lane's d goes through its own LDS slots (no other lane
-    // reads them); U_in is reloaded for the combine instead of being held
+    // reads them)
     T* my = xw + lane;
     sweep_core_streamed<S, T, 0, MB>(P, W, pos, pc, tc, [&](int q, T v) { my[q * kWave] = v; });
 #pragma unroll
@@ -543,7 +549,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) {
       // an output lane is an interior cell: U_in is its own load
-      const T ui = S::S ? Uin[q * P.fs + c] : Uc[q];
+      const T ui = S::S ? xu[q * kWave + lane] : Uc[q];
       const T ust = ui - dtt * d[q];
       if (stage == 0) {
         Un[q] = (rigid && q != S::R) ? ui : ust;
@@ -616,9 +622,9 @@ __device__ inline T* dyn_lds() {
 }
 
 // LDS bytes of an x-sweep block of wpb wavefronts: the elastoplastic sweeps
-// stage each wavefront's streamed d (nfields x 64 values).
+// stage each wavefront's streamed d and its U_in (2 x nfields x 64 values).
 template <class S, typename T>
-constexpr unsigned x_sweep_lds(int wpb) { return S::S ? (unsigned)(wpb * S::NF * kWave * sizeof(T)) : 0u; }
+constexpr unsigned x_sweep_lds(int wpb) { return S::S ? (unsigned)(wpb * 2 * S::NF * kWave * sizeof(T)) : 0u; }
 
 template <class S>
 constexpr int x_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 4; }
@@ -639,9 +645,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
     // per-wavefront staging of the streamed d, sized by the launch for the
     // block's wavefronts (a static size for the largest block would hold
     // LDS that 1- and 2-wavefront blocks never use and cap their occupancy)
-    T* xlds = dyn_lds<T>();
+    T* xlds = dyn_lds<T>() + (threadIdx.x / kWave) * 2 * S::NF * kWave;
     sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
-                                         wpb, nparts, xlds + (threadIdx.x / kWave) * S::NF * kWave);
+                                         wpb, nparts, xlds, xlds + S::NF * kWave);
   } else {
     sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
                                          wpb, nparts);

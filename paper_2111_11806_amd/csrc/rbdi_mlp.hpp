@@ -637,11 +637,15 @@ struct SurrogateSources {
 };
 
 // The final x sweep with the surrogate sources. LDS per wavefront: the
-// streamed d, then (once d has been read back) the network's tile.
+// streamed d, then (once d has been read back) the network's tile; and the
+// wavefront's U_in for the combine.
 template <class S, typename T>
-union XSurrLds {
-  T d[S::NF * kWave];
-  MlpWaveLds mlp;
+struct XSurrLds {
+  union {
+    T d[S::NF * kWave];
+    MlpWaveLds mlp;
+  };
+  T u[S::NF * kWave];  // the wavefront's U_in, kept for the combine
 };
 
 template <class S, typename T, bool MB = false>
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
   XSurrLds<S, T>* my = &lds[threadIdx.x / kWave];
   SurrogateSources src{m, &my->mlp, sc};
   sweep_x_body<S, T, SurrogateSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
-                                           wpb, nparts, my->d, src);
+                                           wpb, nparts, my->d, my->u, src);
 }
 
 }  // namespace rbdi
