@@ -272,8 +272,9 @@ def copper_accuracy(prob, net, nsteps, stream):
     conserved field over the non-rigid cells (rigid cells hold seeded ghost
     states), beside the floor that FP32 storage of the state alone sets: the
     FP64 path with its state rounded to FP32 after every step (rounded on
-    the device). Reported just before the contact (t = 0.45 us) and after
-    nsteps steps (t past the contact)."""
+    the device). Reported just before the contact (t = 0.45 us), after
+    nsteps steps (t past the contact), and for one further step of the FP32
+    paths from the FP64 state (the error a single step adds)."""
     import torch
     from paper_2111_11806_amd import rbdi
     a = rbdi.Solver(prob, "fp64", stream=stream)
@@ -306,6 +307,18 @@ def copper_accuracy(prob, net, nsteps, stream):
         t += dt
         k += 1
     out["through_contact"] = dict(report(), steps=k)
+    # one step of the FP32 paths from the FP64 state (their own times match:
+    # they took the same dt sequence): the error a single step adds
+    ua = a.get_state_cons()
+    b.set_state_cons(ua)
+    e.set_state_cons(ua)
+    dt = a.compute_dt(prob.cfl)
+    for s in (a, b, e):
+        s.step(dt)
+    ua = a.get_state_cons()
+    keep = ua[ir] <= 0.5
+    out["one_step_from_fp64_state"] = {"t": a.t, "surrogate_fp32": field_errors(ua, b.get_state_cons(), names, keep),
+                                       "exact_fp32": field_errors(ua, e.get_state_cons(), names, keep)}
     for s in (a, b, e, c):
         s.close()
     return out
@@ -551,6 +564,10 @@ def main():
                          "fp32_storage_floor_max_l1": worst_l1(acc[when]["fp32_storage_floor"]),
                          "t": acc[when]["t"], "steps": acc[when]["steps"]}
                   for when in ("before_contact", "through_contact") if when in acc}
+        one = acc["one_step_from_fp64_state"]
+        stated["one_step_from_fp64_state"] = {"fp32_surrogate_vs_fp64_max_l1": worst_l1(one["surrogate_fp32"]),
+                                              "fp32_exact_vs_fp64_max_l1": worst_l1(one["exact_fp32"]),
+                                              "t": one["t"]}
     out = {"metric": "cell-updates/s per step (FP32+surrogate vs FP64 plain) at stated L1 error; HBM GB/s %",
            "value": L64["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": L64["ms_per_step"], "higher_is_better": True,
