@@ -137,9 +137,10 @@ typedef struct {
 } rbdi_stats;
 
 /* Create an instance on the current HIP device. Allocates every device buffer
- * the handle owns (three state copies plus scratch); *out receives the
- * handle, which rbdi_destroy releases. Errors: BAD_ARG (invalid desc),
- * OOM, HIP. */
+ * the handle owns (three state copies, one accumulator of the direction
+ * sweeps -- two in 3D -- plus band, reduction and staging scratch); *out
+ * receives the handle, which rbdi_destroy releases. Errors: BAD_ARG (invalid
+ * desc), OOM, HIP. */
 RBDI_API int rbdi_create(const rbdi_desc* desc, rbdi_handle** out);
 
 /* Release the handle and its device memory (synchronises its stream). */

@@ -10,6 +10,7 @@ FP64 oracle, per conserved field (parity_util.BARS):
   times the drift of the ulp-noise / FP32-storage twins of the oracle
   (rounding grows under plastic flow, parity_util.FLOOR_FACTOR);
 - the extrusion at its full 2048 x 1728 uniform grid, 4 steps, FP64;
+- two spheres in 3D, one static, one translating and spinning;
 - the table's argument checks and the single-body call's equality with a
   one-row table.
 """
@@ -78,6 +79,43 @@ def test_one_row_table_equals_single_motion(rbdi):
     for s in (a, b):
         s.advance(prob.cfl, 50, prob.t_end)
     assert np.array_equal(a.get_state_cons(), b.get_state_cons())
+
+
+def test_two_spheres_3d_fp64(rbdi):
+    """3D: a static sphere (body 0) and a translating, spinning sphere (body
+    1, owning x >= 0.5) in a pressure pulse, 28^3, 15 steps: the launches
+    with the ownership test in every 3D kernel against the oracle. (The
+    spheres' diffuse tails reach the box face at this resolution; both sides
+    apply the same ownership rule there.)"""
+    n = 28
+    prob = inputs.periodic_box(dim=3, n=n, nmat=1)
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    W = np.zeros((6, n, n, n))
+    W[0] = np.where(X < 0.15, 1.5, 1.0)
+    W[1] = np.where(X < 0.15, 0.6, 0.0)
+    W[4] = np.where(X < 0.15, 1.8, 1.0)
+    prob.W0 = W
+    prob.bc = ["transmissive"] * 6
+    prob.seed = "original"
+    prob.name = "two_spheres"
+    s0 = np.sqrt((X - 0.3) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) - 0.12
+    s1 = np.sqrt((X - 0.72) ** 2 + (Y - 0.45) ** 2 + (Z - 0.55) ** 2) - 0.12
+    prob.sdf = np.minimum(s0, s1)
+    prob.v_r, prob.omega, prob.center = (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.3, 0.5, 0.5)
+    prob.bodies = (dict(v=(-0.3, 0.05, 0.1), omega=(0.0, 0.8, -0.4), center=(0.72, 0.45, 0.55),
+                        box_lo=(0.5, -math.inf, -math.inf), box_hi=(math.inf, math.inf, math.inf)),)
+    announce("two spheres 3D 28^3 fp64, 15 steps")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(nsteps=15)
+    g = rbdi.Solver(prob, "fp64")
+    g.run(dts)
+    assert g.status()["nonphysical"] == 0
+    check_fields(g.get_state_cons(), orc.get_state_cons(), prob.cons_names(), "fp64", "two spheres 3D fp64")
+    # the moving sphere's r has moved: its r = 0.5 surface no longer where it started
+    r0 = (0.5 * (1.0 - np.tanh(prob.sdf * n)))
+    r = orc.get_state_cons()[prob.cons_names().index("r")]
+    assert np.abs(r - r0)[X > 0.5].max() > 0.1 and np.abs(r - r0)[X < 0.45].max() < 1e-12
 
 
 @pytest.fixture(scope="module")
