@@ -479,6 +479,12 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   const int posl = pos < nd + kHalo ? pos : nd + kHalo - 1;
   const int pc[3] = {posl, j, k};
   const double tc = sc->t[A.par] - sc->t_motion;
+  const bool outlane0 = lane >= kHalo && lane < kHalo + kOut && pos < nd;
+  const long long c0 = outlane0 ? cell_index(P, pos, j, k) : 0;
+  bool rigid0 = false;
+  if constexpr (S::S) {
+    if (outlane0 && !A.rhs_only) rigid0 = (double)U0[S::R * P.fs + c0] > 0.5;
+  }
   T W[S::NF], Uc[S::NF];  // Uc: this lane's U_in, reused by the combine
   {
     int src, face;
@@ -486,14 +492,29 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     if (mode != 2) {
       load_cons<S>(P, Uin, cell_index(P, src, j, k), Uc);
       if constexpr (S::S) {
-        // kept for the combine in this lane's own LDS slots (read back by
-        // the same lane: no barrier) rather than in registers or reloaded
+        // the part of the RK combine that does not depend on d, formed now
+        // (its loads overlap U_in's) and kept in this lane's own LDS slots
+        // (read back by the same lane: no barrier): U_in in the first stage,
+        // U^n + b (U_in - U^n) in the others, U^n in rigid cells
+        const T b = (T)bcoef;
 #pragma unroll
-        for (int q = 0; q < S::NF; ++q) xu[q * kWave + lane] = Uc[q];
+        for (int q = 0; q < S::NF; ++q) {
+          T w = Uc[q];
+          if (stage != 0 && outlane0 && !A.rhs_only) {
+            const T u0 = U0[q * P.fs + c0];
+            w = (rigid0 && q != S::R) ? u0 : u0 + b * (Uc[q] - u0);
+          }
+          xu[q * kWave + lane] = w;
+        }
       }
       cons_to_prim<S>(P, Uc, W);
     }
     ghost_fix<S, T, 0>(P, mode, face, W);
+  }
+  T dpre[S::NF];
+  if (S::S && S::D == 3 && Dacc2 && outlane0 && !A.rhs_only) {
+#pragma unroll
+    for (int q = 0; q < S::NF; ++q) dpre[q] = Dacc[q * P.fs + c0] + Dacc2[q * P.fs + c0];
   }
   T d[S::NF];
   if constexpr (S::S) {
@@ -519,7 +540,10 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     // In 3D the z and y sweeps leave their parts in D and D2 (a y sweep
     // that added into D read it back first); both are added here in the
     // order d_z + d_y + d_x.
-    if (S::D == 3 && Dacc2) {
+    if (S::S && S::D == 3 && Dacc2 && !A.rhs_only) {
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) d[q] = (q == S::R && P.r_static) ? d[q] : dpre[q] + d[q];
+    } else if (S::D == 3 && Dacc2) {
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) {
         const T dq = Dacc[q * P.fs + c] + Dacc2[q * P.fs + c];
@@ -545,17 +569,27 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   if (outlane) {
     const T dtt = (T)dt;
     const T b = (T)bcoef;
-    rigid = (double)U0[S::R * P.fs + c] > 0.5;
+    if constexpr (S::S) {
+      rigid = rigid0;
+      const T coef = stage == 0 ? dtt : b * dtt;
 #pragma unroll
-    for (int q = 0; q < S::NF; ++q) {
-      // an output lane is an interior cell: U_in is its own load
-      const T ui = S::S ? xu[q * kWave + lane] : Uc[q];
-      const T ust = ui - dtt * d[q];
-      if (stage == 0) {
-        Un[q] = (rigid && q != S::R) ? ui : ust;
-      } else {
-        const T u0 = U0[q * P.fs + c];
-        Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
+      for (int q = 0; q < S::NF; ++q) {
+        const T w = xu[q * kWave + lane];
+        Un[q] = (rigid && q != S::R) ? w : w - coef * d[q];
+      }
+    } else {
+      rigid = (double)U0[S::R * P.fs + c] > 0.5;
+#pragma unroll
+      for (int q = 0; q < S::NF; ++q) {
+        // an output lane is an interior cell: U_in is its own load
+        const T ui = Uc[q];
+        const T ust = ui - dtt * d[q];
+        if (stage == 0) {
+          Un[q] = (rigid && q != S::R) ? ui : ust;
+        } else {
+          const T u0 = U0[q * P.fs + c];
+          Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
+        }
       }
     }
   }
