@@ -459,7 +459,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
                                              T* __restrict__ Uout,
                                              DevScalars* __restrict__ sc, double* __restrict__ cflpart,
                                              const StepArgs& A, double bcoef, int stage, int bx, int by, int bz,
-                                             long long blin, int wpb, int nparts, T* xw = nullptr, T* xu = nullptr,
+                                             long long blin, int wpb, int nparts, T* xw = nullptr, double* xu = nullptr,
                                              const Src& src = Src()) {
   const double dt = A.rhs_only ? 1.0 : sc->dtv[A.par];
   if (dt == 0.0) return;  // uniform over the grid
@@ -482,9 +482,6 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   const bool outlane0 = lane >= kHalo && lane < kHalo + kOut && pos < nd;
   const long long c0 = outlane0 ? cell_index(P, pos, j, k) : 0;
   bool rigid0 = false;
-  if constexpr (S::S) {
-    if (outlane0 && !A.rhs_only) rigid0 = (double)U0[S::R * P.fs + c0] > 0.5;
-  }
   T W[S::NF], Uc[S::NF];  // Uc: this lane's U_in, reused by the combine
   {
     int src, face;
@@ -493,18 +490,23 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
       load_cons<S>(P, Uin, cell_index(P, src, j, k), Uc);
       if constexpr (S::S) {
         // the part of the RK combine that does not depend on d, formed now
-        // (its loads overlap U_in's) and kept in this lane's own LDS slots
-        // (read back by the same lane: no barrier): U_in in the first stage,
-        // U^n + b (U_in - U^n) in the others, U^n in rigid cells
-        const T b = (T)bcoef;
+        // and kept in FP64 in this lane's own LDS slots (read back by the
+        // same lane: no barrier): U^n + b (U_in - U^n), U^n in rigid cells;
+        // the FP32 path then rounds the stage result once. U^n is loaded
+        // right behind U_in by every lane, in every stage, in one batch:
+        // lanes outside the output range read cell 0 and their slots are
+        // never read back, and the first stage (b = 1), whose input is U^n
+        // itself, reads the lines U_in's loads have just fetched. Loads
+        // guarded per lane or per stage measured several times slower: the
+        // guard made each one wait for the one before or for all of U_in.
+        T u0v[S::NF];
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q) u0v[q] = U0[q * P.fs + c0];
+        rigid0 = outlane0 && !A.rhs_only && (double)u0v[S::R] > 0.5;
 #pragma unroll
         for (int q = 0; q < S::NF; ++q) {
-          T w = Uc[q];
-          if (stage != 0 && outlane0 && !A.rhs_only) {
-            const T u0 = U0[q * P.fs + c0];
-            w = (rigid0 && q != S::R) ? u0 : u0 + b * (Uc[q] - u0);
-          }
-          xu[q * kWave + lane] = w;
+          const double u0 = (double)u0v[q];
+          xu[q * kWave + lane] = (rigid0 && q != S::R) ? u0 : u0 + bcoef * ((double)Uc[q] - u0);
         }
       }
       cons_to_prim<S>(P, Uc, W);
@@ -512,7 +514,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     ghost_fix<S, T, 0>(P, mode, face, W);
   }
   T dpre[S::NF];
-  if (S::S && S::D == 3 && Dacc2 && outlane0 && !A.rhs_only) {
+  if (S::S && S::D == 3 && Dacc2 && !A.rhs_only) {  // all lanes, as U^n
 #pragma unroll
     for (int q = 0; q < S::NF; ++q) dpre[q] = Dacc[q * P.fs + c0] + Dacc2[q * P.fs + c0];
   }
@@ -571,11 +573,11 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
     const T b = (T)bcoef;
     if constexpr (S::S) {
       rigid = rigid0;
-      const T coef = stage == 0 ? dtt : b * dtt;
+      const double coef = stage == 0 ? dt : bcoef * dt;
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) {
-        const T w = xu[q * kWave + lane];
-        Un[q] = (rigid && q != S::R) ? w : w - coef * d[q];
+        const double w = xu[q * kWave + lane];
+        Un[q] = (T)((rigid && q != S::R) ? w : w - coef * (double)d[q]);
       }
     } else {
       rigid = (double)U0[S::R * P.fs + c] > 0.5;
@@ -656,9 +658,12 @@ __device__ inline T* dyn_lds() {
 }
 
 // LDS bytes of an x-sweep block of wpb wavefronts: the elastoplastic sweeps
-// stage each wavefront's streamed d and its U_in (2 x nfields x 64 values).
+// stage each wavefront's streamed d (nfields x 64 values of T) and the
+// d-independent part of its RK combine (nfields x 64 FP64 values).
 template <class S, typename T>
-constexpr unsigned x_sweep_lds(int wpb) { return S::S ? (unsigned)(wpb * 2 * S::NF * kWave * sizeof(T)) : 0u; }
+constexpr unsigned x_sweep_lds(int wpb) {
+  return S::S ? (unsigned)(wpb * S::NF * kWave * (sizeof(T) + sizeof(double))) : 0u;
+}
 
 template <class S>
 constexpr int x_sweep_waves() { return S::S ? 2 : S::N != 1 ? 1 : 4; }
@@ -679,9 +684,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_sweep_wav
     // per-wavefront staging of the streamed d, sized by the launch for the
     // block's wavefronts (a static size for the largest block would hold
     // LDS that 1- and 2-wavefront blocks never use and cap their occupancy)
-    T* xlds = dyn_lds<T>() + (threadIdx.x / kWave) * 2 * S::NF * kWave;
+    unsigned char* base = dyn_lds<unsigned char>() + (threadIdx.x / kWave) * x_sweep_lds<S, T>(1);
+    T* xd = reinterpret_cast<T*>(base);
+    double* xu = reinterpret_cast<double*>(base + S::NF * kWave * sizeof(T));
     sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
-                                         wpb, nparts, xlds, xlds + S::NF * kWave);
+                                         wpb, nparts, xd, xu);
   } else {
     sweep_x_body<S, T, ExactSources, MB>(P, Uin, U0, Dacc, Dacc2, Uout, sc, cflpart, A, bcoef, stage, bx, by, bz, blin,
                                          wpb, nparts);

@@ -638,14 +638,14 @@ struct SurrogateSources {
 
 // The final x sweep with the surrogate sources. LDS per wavefront: the
 // streamed d, then (once d has been read back) the network's tile; and the
-// wavefront's U_in for the combine.
+// d-independent part of the wavefront's RK combine.
 template <class S, typename T>
 struct XSurrLds {
   union {
     T d[S::NF * kWave];
     MlpWaveLds mlp;
   };
-  T u[S::NF * kWave];  // the wavefront's U_in, kept for the combine
+  double u[S::NF * kWave];  // the d-independent part of the wavefront's RK combine
 };
 
 template <class S, typename T, bool MB = false>
