@@ -535,6 +535,20 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
   }
   const bool outlane = lane >= kHalo && lane < kHalo + kOut && pos < nd;
   const long long c = outlane ? cell_index(P, pos, j, k) : 0;
+  // gas: U^n for the combine (its r row in the first stage) is loaded here,
+  // beside D, in one batch; loads inside the combine's per-field selects
+  // waited for each field in turn
+  T u0v[S::NF];
+  if constexpr (!S::S) {
+    if (outlane && !A.rhs_only) {
+      u0v[S::R] = U0[S::R * P.fs + c];
+      if (stage != 0) {  // uniform over the grid
+#pragma unroll
+        for (int q = 0; q < S::NF; ++q)
+          if (q != S::R) u0v[q] = U0[q * P.fs + c];
+      }
+    }
+  }
   if (outlane && S::D > 1) {
     // with a static body r's operator is zero and the y/z sweeps do not
     // store its row of D: the loaded value is discarded by a select (a
@@ -580,7 +594,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
         Un[q] = (T)((rigid && q != S::R) ? w : w - coef * (double)d[q]);
       }
     } else {
-      rigid = (double)U0[S::R * P.fs + c] > 0.5;
+      rigid = (double)u0v[S::R] > 0.5;
 #pragma unroll
       for (int q = 0; q < S::NF; ++q) {
         // an output lane is an interior cell: U_in is its own load
@@ -589,7 +603,7 @@ __device__ __forceinline__ void sweep_x_body(const Params& P, const T* __restric
         if (stage == 0) {
           Un[q] = (rigid && q != S::R) ? ui : ust;
         } else {
-          const T u0 = U0[q * P.fs + c];
+          const T u0 = u0v[q];
           Un[q] = (rigid && q != S::R) ? u0 : u0 + b * (ust - u0);
         }
       }
