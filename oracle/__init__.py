@@ -44,6 +44,12 @@ What pins each part of the oracle (tests marked ``not gpu``):
   pressure fields.
 * Elastoplastic closure: Hencky strain of diagonal and rotated stretches,
   elastic wave speed and plastic return invariants.
+* Void-opening face modifier (Sec. 3.2, end): an elastic copper slab striking
+  a rigid wall against the elastic-wave estimate (contact pressure, contact
+  time 2 L / c_L, rebound at the impact speed); without the modifier the
+  wall holds the slab; a slab at rest on the wall stays at rest. The gap
+  gas that fills the opening (the reading taken for the deferred void model)
+  is pinned only through the rebound.
 
 Parity unpinned: the readings that no external solution distinguishes (the
 exact HLLC-LM constants beyond the Ma^2 scaling, the phi star state, the
@@ -122,6 +128,7 @@ def lib(variant=None):
             L.orc_set_rigid_sdf.argtypes = [vp, dp, ctypes.c_double, dp, dp, dp]
             L.orc_set_rigid_motion.argtypes = [vp, dp, dp, dp]
             L.orc_set_rigid_bodies.argtypes = [vp, ip, dp, dp, dp, dp, dp]
+            L.orc_set_face_mod.argtypes = [vp, ip, dp]
             L.orc_compute_dt.restype = ctypes.c_double
             L.orc_compute_dt.argtypes = [vp, ctypes.c_double]
             L.orc_step.argtypes = [vp, ctypes.c_double]
@@ -222,6 +229,15 @@ class Oracle:
             self.set_rigid_sdf(prob.sdf, prob.width, prob.v_r, prob.omega, prob.center)
         if prob.bodies:
             self.set_rigid_bodies(*prob.body_table())
+        if prob.gap_gas is not None:
+            self.set_face_mod(1, prob.gap_gas)
+
+    def set_face_mod(self, mode, gap_gas=None):
+        """Void-opening face modifier at solid-rigid faces: mode 0 off, 1 on;
+        gap_gas: primitive state of the gas that fills an opening gap."""
+        W = None if gap_gas is None else _dp(_arr(gap_gas, self.nf))
+        if self._L.orc_set_face_mod(self._h, int(mode), W) != 0:
+            raise ValueError("orc_set_face_mod: mode must be 0 or 1")
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -243,6 +243,11 @@ struct Oracle {
   int plastic = 1;
   double beta_thinc = 1.6;
   double lm_mach = 0.1;
+  // Void-opening face modifier at solid-rigid faces (Sec. 3.2, end): off by
+  // default; when on, gap_W is the primitive state of the gas that fills an
+  // opening gap.
+  int face_mod = 0;
+  double gap_W[kMaxF] = {};
   int nmat = 1, solid_phase = -1;
   Material mat[kMaxMat];
   // Rigid motions: body 0 moves every point no other body claims; body
@@ -609,7 +614,7 @@ struct Oracle {
   // phi = sin(min(1, Ma/0.1) pi/2), Ma = max(|uL|/cL, |uR|/cR) (normal
   // velocity components).
   void hllc(const double* WL, const double* WR, int d, double* Fo, double& ustar,
-            double Vstar[3]) const {
+            double Vstar[3], double* pstar = nullptr) const {
     const int nt = L.n - 1;  // thermodynamic fields (r excluded)
     double UL[kMaxF], UR[kMaxF], FL[kMaxF], FR[kMaxF], UsL[kMaxF], UsR[kMaxF];
     prim_to_cons(WL, UL);
@@ -626,6 +631,8 @@ struct Oracle {
     const double SR = std::max(uL + cL, uR + cR);
     const double Ss = (PR - PL + tl.rho * uL * (SL - uL) - tr.rho * uR * (SR - uR)) /
                       (tl.rho * (SL - uL) - tr.rho * (SR - uR));
+    // normal traction (compression positive) on the contact of the fan
+    if (pstar) *pstar = PL + tl.rho * (SL - uL) * (Ss - uL);
     double chiL, chiR;
     star_state(WL, UL, tl, d, SL, Ss, UsL, chiL);
     star_state(WR, UR, tr, d, SR, Ss, UsR, chiR);
@@ -680,6 +687,33 @@ struct Oracle {
       for (int q = 0; q < nt; ++q) Fo[q] = FR[q];
       ustar = uR;
     }
+  }
+
+  // Void-opening face modifier (Sec. 3.2, end): applied at a face whose two
+  // cells lie on either side of the rigid surface, (0.5 - r_L)(0.5 - r_R) < 0.
+  // Reading (the modifier is defined in other work): the face sees the
+  // material cell's face state against its mirror image about the face
+  // (normal velocity reflected about the rigid velocity, Vbar conjugated by
+  // the reflection), i.e. an exact wall; where the normal traction on that
+  // wall's contact is tensile the solid is let go: the rigid side is replaced
+  // by the gap gas (gap_W, moving with the body's normal velocity, at rest
+  // tangentially), which then flows into the opening gap. real: the material
+  // side's face state; real_left: it lies left of the face.
+  void wall_face(const double* real, bool real_left, int d, const double v[3], double* Fo, double& ust,
+                 double vst[3]) const {
+    double nrm[3] = {0, 0, 0}, m[kMaxF];
+    nrm[d] = 1.0;
+    mirror_state(real, nrm, v, m);
+    double ps;
+    if (real_left) hllc(real, m, d, Fo, ust, vst, &ps);
+    else hllc(m, real, d, Fo, ust, vst, &ps);
+    if (!(ps < 0.0)) return;
+    double gW[kMaxF];
+    for (int q = 0; q < L.n; ++q) gW[q] = gap_W[q];
+    for (int a = 0; a < dim; ++a) gW[L.wU(a)] = (a == d) ? v[d] : 0.0;
+    gW[L.wR()] = m[L.wR()];
+    if (real_left) hllc(real, gW, d, Fo, ust, vst);
+    else hllc(gW, real, d, Fo, ust, vst);
   }
 
   // ---- semi-discrete operator (Sec. 3.1, spatial operator D_ijk) ----------
@@ -749,16 +783,20 @@ struct Oracle {
         for (int i = -1; i <= nd - 1; ++i) {
           const double* wl = &selR[(size_t)(i + 1) * nv];  // right face of cell i
           const double* wr = &selL[(size_t)(i + 2) * nv];  // left face of cell i+1
-          double Fo[kMaxF], ust, vst[3];
-          hllc(wl, wr, d, Fo, ust, vst);
-          for (int q = 0; q < nt; ++q) Ff[(size_t)(i + 1) * nt + q] = Fo[q];
-          us[i + 1] = ust;
-          for (int b = 0; b < 3; ++b) Vs[(size_t)(i + 1) * 3 + b] = vst[b];
           double xf[3];
           for (int e = 0; e < 3; ++e) xf[e] = (e < dim) ? xc(e, p0[e]) : 0.0;
           xf[d] = x0[d] + (i + 1) * dx[d];
           double v[3];
           rigid_velocity(xf, v);
+          double Fo[kMaxF], ust, vst[3];
+          const double rci = Wat(L.wR(), i), rcj = Wat(L.wR(), i + 1);
+          if (face_mod && (0.5 - rci) * (0.5 - rcj) < 0.0)
+            wall_face(rci < 0.5 ? wl : wr, rci < 0.5, d, v, Fo, ust, vst);
+          else
+            hllc(wl, wr, d, Fo, ust, vst);
+          for (int q = 0; q < nt; ++q) Ff[(size_t)(i + 1) * nt + q] = Fo[q];
+          us[i + 1] = ust;
+          for (int b = 0; b < 3; ++b) Vs[(size_t)(i + 1) * 3 + b] = vst[b];
           const double vd = v[d];
           vface[i + 1] = vd;
           const double rL = wl[L.wR()], rR = wr[L.wR()];
@@ -1415,6 +1453,19 @@ ORC_API int orc_set_rigid_bodies(void* h, int nbody, const double* v, const doub
       o->box_lo[k][a] = k > 0 ? lo[3 * k + a] : 0.0;
       o->box_hi[k][a] = k > 0 ? hi[3 * k + a] : 0.0;
     }
+  return 0;
+}
+
+// Void-opening face modifier: mode 0 off (default), 1 on; Wgap: primitive
+// state of the gas that fills an opening gap (its velocity and r are set per
+// face). Returns -1 for another mode or a fluid system.
+ORC_API int orc_set_face_mod(void* h, int mode, const double* Wgap) {
+  Oracle* o = static_cast<Oracle*>(h);
+  if (mode != 0 && mode != 1) return -1;
+  if (mode == 1 && !o->L.solid) return -1;  // elastoplastic systems only
+  o->face_mod = mode;
+  if (Wgap)
+    for (int q = 0; q < o->L.n; ++q) o->gap_W[q] = Wgap[q];
   return 0;
 }
 

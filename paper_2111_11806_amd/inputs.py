@@ -53,6 +53,9 @@ class Problem:
     # center and its ownership box box_lo, box_hi (3-tuples); v_r, omega and
     # center above are body 0's, which moves every point no box claims
     bodies: tuple = ()
+    # primitive state of the gas that fills a gap opening between a solid and
+    # a rigid body; when set, the void-opening face modifier is on
+    gap_gas: Optional[np.ndarray] = None
     recon: str = "bvd_thinc"
     riemann: str = "hllc"
     seed: str = "original"
@@ -490,3 +493,55 @@ def copper_piston_1d(n=400, v_p=30.0, length=10e-3, x_p=1e-3, eps=1e-6, t_end=1.
                    materials=mats, solid=True, bc=["transmissive"] * 6, W0=W, sdf=sdf, width=1.0,
                    v_r=(v_p, 0.0, 0.0), center=(x_p, 0.0, 0.0), recon="muscl", riemann="hllc", cfl=0.4,
                    t_end=t_end)
+
+
+def copper_slab_wall(n=600, v=-20.0, length=12e-3, x_w=1e-3, slab=6e-3, eps=1e-6, t_end=4.0e-6,
+                     face_mod=True, plastic=False, dim=1, axis=0, ntrans=4):
+    """Elastic copper slab (Romenskii, rho0 8930, G0 46 GPa; plasticity off by
+    default) of thickness `slab` across axis `axis`, touching a static rigid
+    wall (body at coordinate < x_w along that axis) and moving into it at
+    v < 0; air around it. n cells along the axis, ntrans along the other
+    axes of a 2D or 3D grid (periodic there). With the void-opening face
+    modifier the slab leaves the wall when the reflected release wave reaches
+    it (after 2 slab / c_L, c_L the longitudinal wave speed), at -v; without
+    it the wall holds the slab in tension."""
+    h = length / n
+    shape = [1, 1, 1]  # nx, ny, nz
+    for e in range(dim):
+        shape[e] = n if e == axis else ntrans
+    x = (np.arange(n) + 0.5) * h
+    cu = dict(TABLE1["copper"])
+    cu.update(rho0=8930.0, G0=46.0e9)
+    nf = 2 * 2 + dim + 1 + 10
+    prof = 0.5 * (np.tanh((x - x_w) / h) - np.tanh((x - x_w - slab) / h))
+    bshape = [1, 1, 1]  # z, y, x order of the arrays
+    bshape[2 - axis] = n
+    ind = np.broadcast_to(prof.reshape(bshape), (shape[2], shape[1], shape[0]))
+    W = np.zeros((nf, shape[2], shape[1], shape[0]))
+    W[0] = eps + (1.0 - 2.0 * eps) * ind   # phi_Cu
+    W[1] = cu["rho0"]
+    W[2] = 1.2
+    W[3 + axis] = v * ind
+    W[3 + dim] = 1.0e5
+    for a in range(3):
+        W[4 + dim + 4 * a] = 1.0
+    gap = np.zeros(nf)
+    gap[0], gap[1], gap[2], gap[3 + dim] = eps, cu["rho0"], 1.2, 1.0e5
+    for a in range(3):
+        gap[4 + dim + 4 * a] = 1.0
+    sdf = np.broadcast_to((x - x_w).reshape(bshape), ind.shape).copy()
+    mats = [romenskii(cu["rho0"], cu["K0"], cu["G0"], cu["alpha"], cu["beta"], cu["Gamma0"], 0.12e9), ideal(1.4)]
+    bc = ["periodic"] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = "transmissive"
+    center = [0.0, 0.0, 0.0]
+    center[axis] = x_w
+    return Problem(name="copper_slab_wall", dim=dim, n=tuple(shape), dx=(h, h, h) if dim > 1 else (h, 1.0, 1.0),
+                   origin=(0.0, 0.0, 0.0), materials=mats, solid=True, bc=bc, W0=W, sdf=sdf, width=1.0,
+                   v_r=(0.0, 0.0, 0.0), center=tuple(center), gap_gas=gap if face_mod else None,
+                   recon="muscl", riemann="hllc", plastic=plastic, cfl=0.4, t_end=t_end)
+
+
+def longitudinal_wave_speed(m):
+    """sqrt((K0 + 4/3 G0) / rho0) of a Romenskii material at its reference
+    state: the elastic wave speed of uniaxial strain."""
+    return float(np.sqrt((m["K0"] + 4.0 / 3.0 * m["G0"]) / m["rho0"]))
