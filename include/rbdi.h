@@ -173,6 +173,22 @@ RBDI_API int rbdi_get_state_cons(rbdi_handle* h, double* U, int on_device);
 /* Set the conserved interior state directly (host or device, FP64). */
 RBDI_API int rbdi_set_state_cons(rbdi_handle* h, const double* U, int on_device);
 
+/* Void-opening face modifier at solid-rigid faces (Sec. 3.2, end: applied
+ * where the rigid fraction crosses 0.5 between the two cells of a face,
+ * (0.5 - r_L)(0.5 - r_R) < 0, so that solids can collide with and separate
+ * from rigid bodies). mode 0: off (the default); mode 1: on. At such a face
+ * the material cell's face state meets its mirror image about the face
+ * (normal velocity reflected about the rigid velocity, Vbar conjugated by the
+ * reflection); where the normal traction on that contact is tensile, the
+ * rigid side becomes the gap gas Wgap (host, FP64, nfields primitives in the
+ * layout of rbdi_set_state_prim; its velocity and r are ignored: it moves with
+ * the body's normal velocity), which then flows into the opening gap (the
+ * paper defers the void model to other work; this reading fills the gap with
+ * the surrounding gas). Elastoplastic systems only; Wgap may be NULL for
+ * mode 0. BAD_ARG for another mode, a fluid system, a NULL or non-finite gap
+ * state. */
+RBDI_API int rbdi_set_face_modifier(rbdi_handle* h, int mode, const double* Wgap);
+
 /* Rigid volume fraction from a signed distance sdf (host or device, FP64,
  * one value per interior cell, negative inside the body; union of bodies =
  * pointwise minimum): r = (1 - tanh(sdf / (width dx_min))) / 2 (Sec. 2.3

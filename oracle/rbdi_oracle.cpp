@@ -690,7 +690,10 @@ struct Oracle {
   }
 
   // Void-opening face modifier (Sec. 3.2, end): applied at a face whose two
-  // cells lie on either side of the rigid surface, (0.5 - r_L)(0.5 - r_R) < 0.
+  // cells lie on either side of the rigid surface, (0.5 - r_L)(0.5 - r_R) < 0,
+  // read as "one cell rigid (r > 0.5), the other not": a cell with r exactly
+  // 0.5 is a material cell, as in the rest of the method (with the strict
+  // product it would shield the wall from the modifier).
   // Reading (the modifier is defined in other work): the face sees the
   // material cell's face state against its mirror image about the face
   // (normal velocity reflected about the rigid velocity, Vbar conjugated by
@@ -790,8 +793,8 @@ struct Oracle {
           rigid_velocity(xf, v);
           double Fo[kMaxF], ust, vst[3];
           const double rci = Wat(L.wR(), i), rcj = Wat(L.wR(), i + 1);
-          if (face_mod && (0.5 - rci) * (0.5 - rcj) < 0.0)
-            wall_face(rci < 0.5 ? wl : wr, rci < 0.5, d, v, Fo, ust, vst);
+          if (face_mod && ((rci > 0.5) != (rcj > 0.5)))
+            wall_face(rci > 0.5 ? wr : wl, !(rci > 0.5), d, v, Fo, ust, vst);
           else
             hllc(wl, wr, d, Fo, ust, vst);
           for (int q = 0; q < nt; ++q) Ff[(size_t)(i + 1) * nt + q] = Fo[q];

@@ -585,6 +585,21 @@ RBDI_API int rbdi_set_bc_state(rbdi_handle* h, int face, const double* W) {
   return RBDI_OK;
 }
 
+RBDI_API int rbdi_set_face_modifier(rbdi_handle* h, int mode, const double* Wgap) {
+  if (!h) return fail(RBDI_ERR_BAD_ARG, "null argument");
+  if (free_member(h)) return RBDI_ERR_NOT_READY;
+  if (mode != 0 && mode != 1) return fail(RBDI_ERR_BAD_ARG, "face modifier mode must be 0 or 1");
+  if (mode == 1 && !h->desc.solid) return fail(RBDI_ERR_BAD_ARG, "the face modifier needs an elastoplastic system");
+  if (mode == 1 && !Wgap) return fail(RBDI_ERR_BAD_ARG, "null gap state");
+  if (mode == 1)
+    for (int q = 0; q < h->nf; ++q) {
+      if (!std::isfinite(Wgap[q])) return fail(RBDI_ERR_BAD_ARG, "non-finite gap state");
+      h->P.gapW[q] = Wgap[q];
+    }
+  h->P.face_mod = mode;
+  return RBDI_OK;
+}
+
 static int stage_in(rbdi_handle* h, const double* src, int on_device) {
   const size_t bytes = (size_t)h->P.ncell * h->nf * sizeof(double);
   HIP_OK(hipMemcpyAsync(h->stage_buf, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,

@@ -325,6 +325,65 @@ __device__ inline void sweep_core(const Params& P, const T* W, int pos, const in
   d[S::R] = ((rfl - rflm) - W[S::R] * (vf - vfm)) * inv;
 }
 
+// Dimensions whose elastoplastic sweeps carry the void-opening face modifier.
+#ifndef RBDI_FACE_MOD_DIMS
+#define RBDI_FACE_MOD_DIMS 3
+#endif
+constexpr int kFaceModDims = RBDI_FACE_MOD_DIMS;
+
+// Void-opening face modifier (Sec. 3.2, end) on the face states of a face
+// whose two cells lie on either side of the rigid surface,
+// (0.5 - r_L)(0.5 - r_R) < 0, taken as one cell rigid (r > 0.5) and the other
+// not, a cell with r = 0.5 being a material cell as everywhere else (cross;
+// real_left: the material cell is the left one). The rigid side's state becomes the mirror image of the material
+// side's (normal velocity reflected about the rigid velocity, Vbar conjugated
+// by the reflection): an exact wall. Where the normal traction on that wall's
+// contact (from the left state of the fan) is tensile, the solid is let go:
+// the rigid side becomes the gap gas (P.gapW, moving with the body's normal
+// velocity, at rest tangentially), which flows into the opening gap. r keeps
+// its face values (its flux is formed apart).
+template <class S, int DIR, bool MB, typename T>
+__device__ inline void face_modifier(const Params& P, int pos, const int* pc, double tc, bool cross, bool real_left,
+                                     T* sR, T* WR) {
+  double v[3] = {0.0, 0.0, 0.0};
+  if (!P.r_static) {
+    double xf[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xf[a] = a < S::D ? P.x0[a] + (pc[a] + 0.5) * P.dx[a] : 0.0;
+    xf[DIR] = P.x0[DIR] + (pos + 1) * P.dx[DIR];
+    rigid_velocity<MB>(P, xf, tc, v);
+  }
+  const T vd = (T)v[DIR];
+#pragma unroll
+  for (int q = 0; q < S::R; ++q) {
+    const T re = real_left ? sR[q] : WR[q];
+    T m = re;
+    if (q == S::wU(DIR)) m = T(2) * vd - re;
+    if constexpr (S::S) {
+      if (q >= S::wV(0, 0) && q < S::wEP) {
+        const int a = (q - S::wV(0, 0)) / 3, b = (q - S::wV(0, 0)) % 3;
+        if ((a == DIR) != (b == DIR)) m = -re;
+      }
+    }
+    WR[q] = (cross && real_left) ? m : WR[q];
+    sR[q] = (cross && !real_left) ? m : sR[q];
+  }
+  HllcFace<S, DIR, T> f;
+  f.init(P, sR, WR);
+  const bool open = cross && (f.L.P + f.L.rho * (f.SL - f.L.un) * (f.Ss - f.L.un)) < 0.0;
+  if (__any(open)) {
+#pragma unroll
+    for (int q = 0; q < S::R; ++q) {
+      T g = (T)P.gapW[q];
+#pragma unroll
+      for (int a = 0; a < S::D; ++a)
+        if (q == S::wU(a)) g = a == DIR ? vd : T(0);
+      WR[q] = (open && real_left) ? g : WR[q];
+      sR[q] = (open && !real_left) ? g : sR[q];
+    }
+  }
+}
+
 // sweep_core for the elastoplastic system, with the same results: the face
 // solver's wave data are built once, then each field's flux, its difference
 // with the left neighbour's and its non-conservative terms are formed one
@@ -358,6 +417,14 @@ __device__ inline void sweep_core_streamed(const Params& P, const T* W, int pos,
   T WR[S::NF];
 #pragma unroll
   for (int q = 0; q < S::NF; ++q) WR[q] = shdn<Z>(sL[q]);
+  if constexpr (kFaceModDims >= S::D) {
+    if (P.face_mod) {  // uniform over the grid
+      const T rn = shdn<Z>(W[S::R]);
+      const bool rig = W[S::R] > T(0.5);
+      const bool cross = rig != (rn > T(0.5));
+      if (__any(cross)) face_modifier<S, DIR, MB>(P, pos, pc, tc, cross, !rig, sR, WR);
+    }
+  }
   HllcFace<S, DIR, T> face;
   face.init(P, sR, WR);
   const T us = (T)face.ustar();

@@ -77,6 +77,10 @@ struct Params {
   double vr[kMaxBody][3], om[kMaxBody][3], ctr[kMaxBody][3];
   double blo[kMaxBody][3], bhi[kMaxBody][3];
   double bcW[6][kMaxF];   // Dirichlet primitive states per face
+  // void-opening face modifier at solid-rigid faces (elastoplastic systems):
+  // on/off, and the primitive state of the gas that fills an opening gap
+  int face_mod;
+  double gapW[kMaxF];
 };
 
 // Compile-time field layout of the reduced-equation multi-material system

@@ -66,7 +66,8 @@ _lib = None
 
 EXPORTS = ["rbdi_create", "rbdi_destroy", "rbdi_nfields", "rbdi_set_stream", "rbdi_set_material",
            "rbdi_set_bc_state", "rbdi_set_state_prim", "rbdi_get_state_prim", "rbdi_get_state_cons",
-           "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_set_rigid_bodies", "rbdi_compute_dt",
+           "rbdi_set_state_cons", "rbdi_set_rigid_sdf", "rbdi_set_rigid_motion", "rbdi_set_rigid_bodies", "rbdi_set_face_modifier",
+           "rbdi_compute_dt",
            "rbdi_step", "rbdi_advance", "rbdi_status", "rbdi_rigid_force", "rbdi_conserved_totals",
            "rbdi_last_error", "rbdi_set_kernel_timing", "rbdi_kernel_times", "rbdi_unit_eval", "rbdi_eval_rhs",
            "rbdi_set_x_waves", "rbdi_autotune",
@@ -106,6 +107,7 @@ def load():
     L.rbdi_set_rigid_sdf.argtypes = [vp, vp, ip, ctypes.c_double, dp, dp, dp]
     L.rbdi_set_rigid_motion.argtypes = [vp, dp, dp, dp]
     L.rbdi_set_rigid_bodies.argtypes = [vp, ip, dp, dp, dp, dp, dp]
+    L.rbdi_set_face_modifier.argtypes = [vp, ip, dp]
     L.rbdi_compute_dt.argtypes = [vp, ctypes.c_double, dp]
     L.rbdi_step.argtypes = [vp, ctypes.c_double]
     L.rbdi_advance.argtypes = [vp, ctypes.c_double, ip, ctypes.c_double]
@@ -218,6 +220,8 @@ class Solver:
             self.set_rigid_sdf(prob.sdf, prob.width, prob.v_r, prob.omega, prob.center)
         if prob.bodies:
             self.set_rigid_bodies(*prob.body_table())
+        if prob.gap_gas is not None:
+            self.set_face_modifier(1, prob.gap_gas)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -286,6 +290,12 @@ class Solver:
         nb = v.shape[0]
         a = [np.ascontiguousarray(x, dtype=np.float64).reshape(nb, 3) for x in (v, omega, center, box_lo, box_hi)]
         _check(load().rbdi_set_rigid_bodies(self._h, nb, *[_dp(x) for x in a]))
+
+    def set_face_modifier(self, mode, gap_gas=None):
+        """Void-opening face modifier at solid-rigid faces: mode 0 off, 1 on;
+        gap_gas: primitive state of the gas that fills an opening gap."""
+        W = None if gap_gas is None else _dp(_arr(gap_gas, self.nf))
+        _check(load().rbdi_set_face_modifier(self._h, int(mode), W))
 
     def compute_dt(self, cfl):
         out = ctypes.c_double()

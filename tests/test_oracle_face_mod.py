@@ -109,3 +109,22 @@ def test_face_mod_arguments():
     of = oracle.Oracle(fluid)
     with pytest.raises(ValueError):
         of.set_face_mod(1, np.zeros(fluid.nfields))
+
+
+def test_wall_through_a_cell_centre():
+    """A wall through a cell centre leaves that cell at r = 0.5 exactly: a
+    material cell, so the modifier acts on the face to its rigid neighbour
+    (the strict product (0.5 - r_L)(0.5 - r_R) < 0 would never hold there and
+    the wall would hold the slab)."""
+    n, length, slab = 150, 3e-3, 1.5e-3
+    h = length / n
+    prob = inputs.copper_slab_wall(n=n, v=V, slab=slab, length=length, x_w=12.5 * h)
+    o = oracle.Oracle(prob)
+    r = o.get_state_prim()[-1, 0, 0]
+    assert np.any(r == 0.5)
+    tc = 2.0 * slab / inputs.longitudinal_wave_speed(prob.materials[0])
+    o.run(t_end=1.5 * tc)
+    U = o.get_state_cons()[:, 0, 0, :]
+    W = o.get_state_prim()[:, 0, 0, :]
+    m = W[-1] < 0.5
+    assert (U[0] * W[3])[m].sum() / U[0][m].sum() == pytest.approx(-V, rel=0.03)
