@@ -27,6 +27,13 @@ HIPCC_FLAGS = [
     # sweeps with the most inlined physics exceed that, and the copy then
     # lands in scratch memory (2 KB per lane).
     "-mllvm", "-instcombine-max-copied-from-constant-users=4000",
+    # No machine-level loop-invariant code motion. A VALU instruction reads at
+    # most one scalar operand, so the sweeps move many material and grid
+    # constants into vector registers; inside the tile sweeps' column loop
+    # that pass hoists those moves out of the loop and keeps them live across
+    # it: the FP32 elastoplastic tile sweeps then spilled 31-47 registers at
+    # 256 VGPRs, and with the moves left at their uses they take 237, no spill.
+    "-mllvm", "-disable-machine-licm",
 ]
 
 
