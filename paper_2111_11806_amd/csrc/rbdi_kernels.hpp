@@ -789,17 +789,18 @@ constexpr int kRS = 65;  // LDS stride of a tile column (padded)
 #define RBDI_TC 16
 #endif
 // Columns of a y/z tile: the widest of 16, 8, 4 whose tile fits the LDS
-// budget: 80 KB (two blocks per CU in its 160 KB) for FP32, 48 KB for FP64.
-// Wider tiles load longer rows (TC consecutive x values) but give each
-// wavefront more columns in sequence: on the 256^3 copper grid the FP32
-// elastoplastic y + z sweeps take 4.9 ms at 16 columns against 5.7 at 8,
-// the FP64 ones 6.4 ms at 4 columns against 7.9 at 8.
-template <typename T>
-constexpr int tile_lds_budget() { return sizeof(T) == 8 ? 48 * 1024 : 80 * 1024; }
+// budget: 80 KB (two blocks per CU in its 160 KB) for FP32 and for the FP64
+// elastoplastic systems, 48 KB for the FP64 fluid ones. Wider tiles load
+// and store longer rows (TC consecutive x values) but give each wavefront
+// more columns in sequence, which costs registers across the column loop:
+// on the 256^3 copper grid the FP64 elastoplastic y + z sweeps take 5.25 ms
+// at 8 columns (64-byte rows) against 5.66 at 4.
+template <class S, typename T>
+constexpr int tile_lds_budget() { return (sizeof(T) == 8 && !S::S ? 48 : 80) * 1024; }
 template <class S, typename T>
 constexpr int tile_cols() {
-  return (S::NF * RBDI_TC * kRS * (int)sizeof(T) <= tile_lds_budget<T>()) ? RBDI_TC
-       : (S::NF * 8 * kRS * (int)sizeof(T) <= tile_lds_budget<T>()) ? 8 : 4;
+  return (S::NF * RBDI_TC * kRS * (int)sizeof(T) <= tile_lds_budget<S, T>()) ? RBDI_TC
+       : (S::NF * 8 * kRS * (int)sizeof(T) <= tile_lds_budget<S, T>()) ? 8 : 4;
 }
 
 template <class S, typename T, int DIR, int MODE, bool REDUCE, bool MB = false>
