@@ -516,7 +516,10 @@ struct ExactSources {
 };
 
 // The final x sweep of a stage. xw: this wavefront's LDS slots of the
-// streamed d (elastoplastic systems; NF x 64 values). src(P, Un, act) applies
+// streamed d (elastoplastic systems; NF x 64 values of T); xu: its slots of
+// the d-independent part of the RK combine (NF x 64 FP64 values; the same
+// systems). Dacc2: the second operator part (3D: the y sweep's), or null
+// where Dacc holds the whole y/z operator. src(P, Un, act) applies
 // the per-cell sources to the updated state Un; every lane of the wavefront
 // calls it (act: the lane holds an updated non-rigid cell), so a source step
 // may work across the wavefront (the surrogate's matrix instructions).
