@@ -128,3 +128,41 @@ def test_wall_through_a_cell_centre():
     W = o.get_state_prim()[:, 0, 0, :]
     m = W[-1] < 0.5
     assert (U[0] * W[3])[m].sum() / U[0][m].sum() == pytest.approx(-V, rel=0.03)
+
+
+@pytest.mark.parametrize("dim,axis", [(2, 1), (3, 2)])
+def test_slab_across_y_or_z_reproduces_the_1d_run(dim, axis):
+    """The modifier in the y (2D) and z (3D) sweeps: a slab uniform across
+    the other (periodic) axes is the 1D problem turned; every column must
+    reproduce the pinned 1D run through the impact and the opening (conserved
+    fields to 1e-10 of each field's largest value: the seeding's probes
+    interpolate across identical columns, which rounds), with the normal
+    momentum and the normal / tangential stretches exchanged."""
+    n, length, slab = 150, 3e-3, 1.5e-3
+    kw = dict(n=n, v=V, slab=slab, length=length, x_w=10 * length / n)
+    p1 = inputs.copper_slab_wall(**kw)
+    pd = inputs.copper_slab_wall(dim=dim, axis=axis, ntrans=3, **kw)
+    o1, od = oracle.Oracle(p1), oracle.Oracle(pd)
+    tc = 2.0 * slab / inputs.longitudinal_wave_speed(p1.materials[0])
+    dts = o1.run(t_end=1.3 * tc)
+    od.run(dts=dts)
+    U1 = o1.get_state_cons()[:, 0, 0, :]
+    Ud = od.get_state_cons()
+    f1, fd = p1.cons_names(), pd.cons_names()
+    mom = "m" + "xyz"[axis]
+    pairs = [("arho0", "arho0"), ("arho1", "arho1"), ("mx", mom), ("E", "E"), ("phi0", "phi0"),
+             ("V00", f"V{axis}{axis}"), ("V11", "V00"), ("V22", "V22" if axis == 1 else "V11"),
+             ("aeps", "aeps"), ("r", "r")]
+    for a, b in pairs:
+        ref = U1[f1.index(a)]
+        col = np.moveaxis(Ud[fd.index(b)], 2 - axis, -1).reshape(-1, n)
+        scale = max(np.abs(ref).max(), 1e-300)
+        assert np.abs(col - ref).max() <= 1e-10 * scale, (a, b, np.abs(col - ref).max() / scale)
+    # the other momentum components stay zero
+    for c in "xyz"[:dim]:
+        if c != "xyz"[axis]:
+            assert np.abs(Ud[fd.index("m" + c)]).max() == 0.0
+    # and the slab has left the wall
+    W1 = o1.get_state_prim()[:, 0, 0, :]
+    m = W1[-1] < 0.5
+    assert (U1[0] * W1[p1.field_names().index("u")])[m].sum() / U1[0][m].sum() > 0.9 * abs(V)
