@@ -47,7 +47,8 @@ What pins each part of the oracle (tests marked ``not gpu``):
 * Void-opening face modifier (Sec. 3.2, end): an elastic copper slab striking
   a rigid wall against the elastic-wave estimate (contact pressure, contact
   time 2 L / c_L, rebound at the impact speed); without the modifier the
-  wall holds the slab; a slab at rest on the wall stays at rest; the same
+  wall holds the slab; a slab at rest on the wall stays at rest, also when
+  the wall starts to move away from it; the same
   slab across y (2D) or z (3D) reproduces the 1D run column by column. The gap
   gas that fills the opening (the reading taken for the deferred void model)
   is pinned only through the rebound.

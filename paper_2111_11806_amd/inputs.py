@@ -496,7 +496,7 @@ def copper_piston_1d(n=400, v_p=30.0, length=10e-3, x_p=1e-3, eps=1e-6, t_end=1.
 
 
 def copper_slab_wall(n=600, v=-20.0, length=12e-3, x_w=1e-3, slab=6e-3, eps=1e-6, t_end=4.0e-6,
-                     face_mod=True, plastic=False, dim=1, axis=0, ntrans=4):
+                     face_mod=True, plastic=False, dim=1, axis=0, ntrans=4, wall_v=0.0):
     """Elastic copper slab (Romenskii, rho0 8930, G0 46 GPa; plasticity off by
     default) of thickness `slab` across axis `axis`, touching a static rigid
     wall (body at coordinate < x_w along that axis) and moving into it at
@@ -504,7 +504,8 @@ def copper_slab_wall(n=600, v=-20.0, length=12e-3, x_w=1e-3, slab=6e-3, eps=1e-6
     axes of a 2D or 3D grid (periodic there). With the void-opening face
     modifier the slab leaves the wall when the reflected release wave reaches
     it (after 2 slab / c_L, c_L the longitudinal wave speed), at -v; without
-    it the wall holds the slab in tension."""
+    it the wall holds the slab in tension. wall_v: the wall's velocity along
+    the axis (negative: it moves away from the slab)."""
     h = length / n
     shape = [1, 1, 1]  # nx, ny, nz
     for e in range(dim):
@@ -535,9 +536,11 @@ def copper_slab_wall(n=600, v=-20.0, length=12e-3, x_w=1e-3, slab=6e-3, eps=1e-6
     bc[2 * axis] = bc[2 * axis + 1] = "transmissive"
     center = [0.0, 0.0, 0.0]
     center[axis] = x_w
+    vr = [0.0, 0.0, 0.0]
+    vr[axis] = wall_v
     return Problem(name="copper_slab_wall", dim=dim, n=tuple(shape), dx=(h, h, h) if dim > 1 else (h, 1.0, 1.0),
                    origin=(0.0, 0.0, 0.0), materials=mats, solid=True, bc=bc, W0=W, sdf=sdf, width=1.0,
-                   v_r=(0.0, 0.0, 0.0), center=tuple(center), gap_gas=gap if face_mod else None,
+                   v_r=tuple(vr), center=tuple(center), gap_gas=gap if face_mod else None,
                    recon="muscl", riemann="hllc", plastic=plastic, cfl=0.4, t_end=t_end)
 
 

@@ -57,6 +57,23 @@ def test_slab_rebound_fp64_parity(rbdi, dim, axis, n, ntrans):
     assert u == pytest.approx(-V, rel=0.04)
 
 
+def test_wall_pulling_away_fp64_parity(rbdi):
+    """A moving wall (the rigid velocity enters the modifier's mirror and gap
+    states; the band is rebuilt every step): the wall leaves a slab at rest at
+    20 m/s, the contact opens and the slab stays at rest."""
+    prob = inputs.copper_slab_wall(n=400, v=0.0, wall_v=V)
+    t_stop = _tc(prob, 6e-3)
+    announce(f"face modifier, wall pulling away, slab 1D n={prob.n} to t={t_stop:.3e} fp64")
+    orc = oracle.Oracle(prob)
+    dts = orc.run(t_end=t_stop)
+    gpu = rbdi.Solver(prob, "fp64")
+    gpu.run(dts)
+    assert gpu.status()["nonphysical"] == 0
+    Ug = gpu.get_state_cons()
+    check_fields(Ug, orc.get_state_cons(), prob.cons_names(), "fp64", "wall pulling away")
+    assert abs(_mean_velocity(prob, Ug, 0)) < 0.01 * abs(V)
+
+
 def test_slab_rebound_fp32(rbdi):
     """FP32 against the oracle. Per step: from the oracle's state while the
     compression wave runs (a quarter of the contact time; at half of it the

@@ -166,3 +166,25 @@ def test_slab_across_y_or_z_reproduces_the_1d_run(dim, axis):
     W1 = o1.get_state_prim()[:, 0, 0, :]
     m = W1[-1] < 0.5
     assert (U1[0] * W1[p1.field_names().index("u")])[m].sum() / U1[0][m].sum() > 0.9 * abs(V)
+
+
+def test_wall_pulling_away_leaves_a_resting_slab_at_rest():
+    """A moving wall (the rigid velocity enters the mirror state): the wall
+    starts to move away from a slab at rest at 20 m/s. With the modifier the
+    contact opens at once and the slab stays at rest (a free face); without
+    it the mirror condition drags the slab after the wall, and the release
+    wave reflected at the slab's free end doubles the pull (mean velocity
+    near twice the wall's after 2 L / c_L)."""
+    w = -20.0
+    res = {}
+    for fm in (True, False):
+        prob = inputs.copper_slab_wall(n=N, v=0.0, slab=SLAB, wall_v=w, face_mod=fm)
+        tc = _tc(prob)
+        o = oracle.Oracle(prob)
+        o.run(t_end=tc)
+        U = o.get_state_cons()[:, 0, 0, :]
+        W = o.get_state_prim()[:, 0, 0, :]
+        m = W[-1] < 0.5
+        res[fm] = (U[0] * W[3])[m].sum() / U[0][m].sum()
+    assert abs(res[True]) < 0.01 * abs(w)
+    assert res[False] < 1.5 * w
