@@ -407,6 +407,44 @@ def run_extrusion(steps, warmup):
     return out
 
 
+def run_slab_wall(steps, n=1024, ntrans=1024):
+    """The void-opening face modifier at work: a 2D elastic copper slab
+    across y (n cells along y, ntrans along x, periodic in x) that has struck
+    a static rigid wall at 20 m/s, FP64, timed over `steps` device CFL steps
+    from 0.95 of its contact time 2 L / c_L (the slab leaves the wall in
+    them), with the modifier on and, for its cost, off (the wall then holds
+    the slab)."""
+    import torch
+    from paper_2111_11806_amd import inputs, rbdi
+    prob = inputs.copper_slab_wall(n=n, dim=2, axis=1, ntrans=ntrans)
+    tc = 2.0 * 6e-3 / inputs.longitudinal_wave_speed(prob.materials[0])
+    dt_est = prob.cfl * prob.dx[1] / inputs.longitudinal_wave_speed(prob.materials[0])
+    stream = torch.cuda.current_stream()
+    out = {"workload": "copper slab rebounding from a rigid wall (2D, 20 m/s)", "nx": prob.n[0], "ny": prob.n[1],
+           "cells": prob.ncells, "dtype": "f64", "steps": steps, "unit": "cell-updates/s",
+           "timed_from_t_over_contact_time": 0.95}
+    for mode in (1, 0):
+        s = rbdi.Solver(prob, "fp64", stream=stream)
+        s.set_face_modifier(mode, prob.gap_gas)
+        s.advance(prob.cfl, int(1.2 * 0.95 * tc / dt_est) + 10, 0.95 * tc)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.advance(prob.cfl, steps, 2.0 * tc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = s.status(raise_on_error=False)
+        out["modifier_on" if mode else "modifier_off"] = {"ms_per_step": round(ms, 4),
+                                                          "value": prob.ncells / (ms * 1e-3),
+                                                          "t_over_contact_time": st["t"] / tc,
+                                                          "nonphysical": st["nonphysical"]}
+        s.close()
+    out["modifier_cost"] = out["modifier_on"]["ms_per_step"] / out["modifier_off"]["ms_per_step"] - 1.0
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -512,6 +550,8 @@ def main():
     ap.add_argument("--no-wedge", action="store_true")
     ap.add_argument("--extrusion-steps", type=int, default=300)
     ap.add_argument("--no-extrusion", action="store_true")
+    ap.add_argument("--slab-steps", type=int, default=300)
+    ap.add_argument("--no-slab", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -596,6 +636,8 @@ def main():
         out["wedge"] = run_wedge(args.wedge_steps, 20)
     if not args.no_extrusion:
         out["extrusion"] = run_extrusion(args.extrusion_steps, 10)
+    if not args.no_slab:
+        out["face_modifier"] = run_slab_wall(args.slab_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(args.cpu_seconds)
         a = cb["all_threads"]
