@@ -11,3 +11,5 @@ if HERE not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    import parity_util
+    parity_util.set_pytest_config(config)

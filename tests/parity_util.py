@@ -167,10 +167,27 @@ def check_fields(a, b, names, precision="fp64", label="", bars=None, field_bars=
     return err
 
 
+_PYTEST_CONFIG = None
+
+
+def set_pytest_config(config):
+    global _PYTEST_CONFIG
+    _PYTEST_CONFIG = config
+
+
 def announce(msg):
-    """Print and flush the case name before a GPU step."""
-    sys.stdout.write("\n[gpu case] %s\n" % msg)
-    sys.stdout.flush()
+    """Print and flush the case name before a GPU step (and the progress of
+    long oracle runs). Under pytest the line goes past output capture to the
+    terminal, so that a long test shows it is alive while it runs."""
+    line = "\n[gpu case] %s\n" % msg
+    capman = _PYTEST_CONFIG.pluginmanager.getplugin("capturemanager") if _PYTEST_CONFIG else None
+    if capman is not None:
+        with capman.global_and_fixture_disabled():
+            sys.stdout.write(line)
+            sys.stdout.flush()
+    else:
+        sys.stdout.write(line)
+        sys.stdout.flush()
 
 
 def gpu_available():
