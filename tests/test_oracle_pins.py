@@ -640,6 +640,34 @@ def test_copper_piston_elastic_precursor_at_hugoniot_elastic_limit():
     assert np.all(W[14][behind] > 1e-3) and np.all(np.abs(W[14][x > front]) < 1e-12)
 
 
+def test_copper_piston_plastic_wave_speed_and_stress():
+    """The same copper piston: behind the elastic precursor the plastic wave
+    runs at the bulk sound speed sqrt(K0/rho0) on top of the precursor's
+    particle velocity u_HEL = HEL / (rho0 c_L) (perfect plasticity holds the
+    deviatoric stress on the yield surface, so only the bulk modulus
+    stiffens the material), and the momentum jump across it gives
+    -sigma_xx = HEL + rho0 c_B (u_p - u_HEL) behind it (small-strain
+    estimates; the copper is compressed by ~0.8%, which stiffens K0 by ~2%)."""
+    K, G, rho0, sY = 130.1e9, 46e9, 8930.0, 0.12e9
+    hel = (K + 4 * G / 3) * sY / (2 * G)
+    cl = math.sqrt((K + 4 * G / 3) / rho0)
+    cb = math.sqrt(K / rho0)
+    u_hel = hel / (rho0 * cl)
+    p = inputs.copper_piston_1d(400)
+    o = oracle.Oracle(p)
+    o.run()
+    W = o.get_state_prim()[:, 0, 0]
+    x = (np.arange(400) + 0.5) * p.dx[0]
+    u = W[3]
+    cut = 0.5 * (u_hel + 30.0)
+    i = np.nonzero(u > cut)[0].max()
+    front = x[i] + (u[i] - cut) / (u[i] - u[i + 1]) * p.dx[0]
+    assert (front - 1e-3) / o.t == pytest.approx(u_hel + cb, rel=0.02)
+    sxx = np.array([-o.thermo(W[:, k])["sigma"][0, 0] for k in range(400)])
+    behind = (x > 1.5e-3) & (x < 4.5e-3)
+    assert np.median(sxx[behind]) == pytest.approx(hel + rho0 * cb * (30.0 - u_hel), rel=0.02)
+
+
 def test_indenter_keeps_mirror_symmetry():
     """The 3D indenter is symmetric under x -> -x and y -> -y about the
     cylinder axis; the elastoplastic step (with first-order fallbacks in
