@@ -43,7 +43,9 @@ What pins each part of the oracle (tests marked ``not gpu``):
 * Force (O.6 reading): summation-by-parts identity, uniform and linear
   pressure fields.
 * Elastoplastic closure: Hencky strain of diagonal and rotated stretches,
-  elastic wave speed and plastic return invariants.
+  elastic wave speed and plastic return invariants; a copper piston's
+  elastic precursor at the Hugoniot elastic limit and its plastic wave at the
+  bulk sound speed with the momentum-jump stress.
 * Void-opening face modifier (Sec. 3.2, end): an elastic copper slab striking
   a rigid wall against the elastic-wave estimate (contact pressure, contact
   time 2 L / c_L, rebound at the impact speed); without the modifier the
@@ -55,8 +57,9 @@ What pins each part of the oracle (tests marked ``not gpu``):
 
 Parity unpinned: the readings that no external solution distinguishes (the
 exact HLLC-LM constants beyond the Ma^2 scaling, the phi star state, the
-solid HLLC variant's star-region flux) are pinned only by internal
-identities.
+solid HLLC variant's star-region flux, the plastic return's exact form per
+stage, the gap gas's velocity) are pinned only by internal identities or by
+what they lead to.
 """
 from __future__ import annotations
 
