@@ -57,9 +57,8 @@ What pins each part of the oracle (tests marked ``not gpu``):
 
 Parity unpinned: the readings that no external solution distinguishes (the
 exact HLLC-LM constants beyond the Ma^2 scaling, the phi star state, the
-solid HLLC variant's star-region flux, the plastic return's exact form per
-stage, the gap gas's velocity) are pinned only by internal identities or by
-what they lead to.
+solid HLLC variant's star-region flux, the gap gas's velocity) are pinned
+only by internal identities or by what they lead to.
 """
 from __future__ import annotations
 
