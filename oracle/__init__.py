@@ -31,7 +31,9 @@ What pins each part of the oracle (tests marked ``not gpu``):
   interaction with the contact, the Rankine-Hugoniot moving piston,
   quiescent preservation around a static body (bitwise), Abgrall interface,
   conservation to 1e-12 with periodic boundaries.
-* Seeding (Sec. 3.2): Householder reflection identities, equality with an
+* Seeding (Sec. 3.2): a flat piston in a channel stays one-dimensional with
+  its normal tilted toward a wall at rounding level (probe points near a
+  domain face); Householder reflection identities, equality with an
   explicit rotate-reflect-rotate-back, the Riemann variant's S* = v_r.n; its
   p* and rho* against linear acoustics for small wall-normal speeds and the
   exact Riemann solution at moderate ones, its stretch against the

@@ -411,6 +411,26 @@ def piston_1d(n=400, v_p=1.0, x_p=0.2, t_end=0.3, recon="muscl"):
                    t_end=t_end)
 
 
+def piston_channel(nx=64, ny=8, tilt=1e-12, v_p=1.0, x_p=0.2):
+    """A flat rigid piston (body x < x_p + tilt y) moving at v_p into gas at
+    rest (1, 0, 1) along a channel with reflective walls (a 1D flow); the
+    tiny tilt turns the body normal toward the lower wall at rounding
+    level."""
+    dx = 1.0 / nx
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    W = np.zeros((5, 1, ny, nx))
+    W[0] = 1.0
+    W[3] = 1.0
+    sdf = (X - x_p - tilt * Y).reshape(1, ny, nx)
+    return Problem(name="piston_channel", dim=2, n=(nx, ny, 1), dx=(dx, dx, dx), origin=(0.0, 0.0, 0.0),
+                   materials=[ideal(1.4)], solid=False,
+                   bc=["transmissive", "transmissive", "reflective", "reflective", "transmissive", "transmissive"],
+                   W0=W, sdf=sdf, width=1.0, v_r=(v_p, 0.0, 0.0), center=(x_p, 0.0, 0.0), recon="muscl",
+                   riemann="hllc", cfl=0.5)
+
+
 def piston_wall_1d(n=800, v_p=1.0, x_p=0.2, x_w=0.8, t_end=0.4, box_cells=20, recon="muscl"):
     """Gas at rest (1, 0, 1) between two rigid bodies with their own motion:
     a piston x < x_p moving at v_p (body 1, owning the points behind its box

@@ -74,6 +74,16 @@ def test_piston_moving_body(rbdi, recon, seed):
     _check(orc, gpu)
 
 
+def test_piston_in_a_channel(rbdi):
+    """A flat piston in a reflective channel, its face tilted at rounding
+    level toward the lower wall: the first row's probes start within half a
+    cell of the outermost centres (pinned on the oracle to keep the flow 1D);
+    the device path seeds them the same way."""
+    prob = inputs.piston_channel()
+    orc, gpu, _ = _pair(rbdi, prob, nsteps=30)
+    _check(orc, gpu)
+
+
 @pytest.mark.parametrize("n", [3, 5, 57, 58, 59, 117, 401])
 def test_ragged_1d_sizes(rbdi, n):
     """Sizes below, at and around the 58-cell wavefront tile, periodic and
